@@ -1,0 +1,77 @@
+"""The pins are strong enough: each plausible mistake, planted in a copy of
+the oracle's C source and compiled on the CPU, fails at least one pin.
+
+The mutants are text substitutions on ``oracle/edge_oracle.c``; each one is
+built into a temporary shared library, swapped in for the real one, and the
+pin tests of ``test_oracle_pins.py`` are run against it.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "edge_oracle.c")
+
+MUTANTS = {
+    "diagonal_for_4nbr": ("FOUR_NEIGHBOURS[4] = {2, 4, 6, 8}", "FOUR_NEIGHBOURS[4] = {2, 4, 6, 7}"),
+    "dropped_neighbour": ("for (int i = 0; i < 4; ++i)", "for (int i = 0; i < 3; ++i)"),
+    "wrong_direction": ("DY[9] = {0, -1, -1, -1, 0, +1, +1, +1, 0}",
+                        "DY[9] = {0, -1, +1, -1, 0, +1, +1, +1, 0}"),
+    "white_is_edge": ("if (p == 0) {", "if (p == 1) {"),
+    "clause2_bound": ("if (black_8 <= 1)", "if (black_8 <= 2)"),
+    "transposed_index": ("return img[y * W + x] != 0;", "return img[x * H + y] != 0;"),
+    "border_ignored": ("return border_pixel;\n    return img", "return 1;\n    return img"),
+    "inverted_colour": ("return img[y * W + x] != 0;", "return img[y * W + x] == 0;"),
+    "invert_ignored": ("(invert ? !edge : edge)", "(edge)"),
+    "clause2_strict": ("if (black_8 <= 1)", "if (black_8 < 1)"),
+}
+
+
+def _pin_suite(golden_dir):
+    """The pin tests, run one after another; returns the first failure."""
+    checks = [
+        lambda: pins.test_fig1_four_neighbours_are_2_4_6_8(golden_dir),
+        lambda: pins.test_fig2_patterns_are_edge_points(golden_dir),
+        lambda: pins.test_fig2_patterns_cover_every_edge_point(golden_dir),
+        lambda: [pins.test_matches_textbook_morphology(s, b, q)
+                 for s in [(17, 33), (1, 7), (7, 1)] for b in pins.BORDERS for q in (0.1, 0.5)],
+        lambda: [pins.test_exhaustive_tiny_images(s) for s in [(3, 3), (2, 5), (1, 4)]],
+        lambda: [pins.test_closed_forms_whole_image(h, w) for h, w in [(1, 9), (5, 8)]],
+        lambda: pins.test_clause2_closed_forms(),
+        lambda: [pins.test_invariants(b) for b in pins.BORDERS],
+    ]
+    for c in checks:
+        try:
+            c()
+        except AssertionError as e:  # the pin caught the mutant
+            return e
+    return None
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path, monkeypatch, golden_dir):
+    old, new = MUTANTS[name]
+    text = open(SRC).read()
+    assert text.count(old) >= 1, f"mutation site for {name} not found"
+    src = tmp_path / "mutant.c"
+    src.write_text(text.replace(old, new, 1))
+    so = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O1", "-std=c99", "-shared", "-fPIC", "-o", str(so), str(src)],
+                   check=True)
+    lib = ctypes.CDLL(str(so))
+    real = oracle._load()
+    for fn in ("oracle_edge_image", "oracle_edge_stack"):
+        getattr(lib, fn).argtypes = getattr(real, fn).argtypes
+        getattr(lib, fn).restype = ctypes.c_int
+    monkeypatch.setattr(oracle, "_lib", lib)
+    assert _pin_suite(golden_dir) is not None, f"mutant {name} survived every pin"
+
+
+def test_unmutated_oracle_passes_suite(golden_dir):
+    assert _pin_suite(golden_dir) is None
+    assert np.array_equal(oracle.edge(np.zeros((2, 2), np.uint8)), np.ones((2, 2), np.uint8))
