@@ -1,0 +1,332 @@
+#!/usr/bin/env python3
+"""Edge Gpixel/s and fraction of HBM peak of the method-of-masks kernels on
+one MI355X, with the CPU oracle timed beside them.
+
+Headline workload: the plain method on one 8192x8192 binary page packed in
+uint64 row words (seeded glyph strokes, about 20% black, 0.5% salt-and-
+pepper), white border. One step = one edge_masks launch over the whole
+image; launches rotate over 40 input/output buffer pairs (640 MiB) so that
+every launch reads from HBM rather than the 256 MB last-level cache.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "edge Gpixel/s & % HBM peak; batched/served vs plain, p50/p99 ms"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--headline-only", action="store_true",
+                   help="time only the headline workload (no other configs, no CPU baseline)")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    return p.parse_args()
+
+
+def ensure_built():
+    from paper_1401_5245_amd import build as hip_build
+    if not os.path.exists(hip_build.LIB):
+        import __graft_entry__
+        __graft_entry__.build()
+
+
+class Timer:
+    """HIP events on torch's current stream, the stream every launch uses."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def per_call_ms(self, fn, n: int) -> float:
+        t = self.torch
+        s = t.cuda.current_stream()
+        a, b = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        a.record(s)
+        for i in range(n):
+            fn(i)
+        b.record(s)
+        b.synchronize()
+        return a.elapsed_time(b) / n
+
+
+def words_tensor(torch, words):
+    wb = words.dtype.itemsize * 8
+    return torch.from_numpy(words.view(np.int64 if wb == 64 else np.int32).copy()).cuda()
+
+
+def roofline(bytes_per_launch: float, ms: float, traffic=None) -> dict:
+    gbs = bytes_per_launch / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+
+def check_rows(img, out_words, width, rows, border="white", clauses=1):
+    """Compare sampled output rows with the oracle run on windows of img."""
+    import oracle
+    from synth import unpack_rows
+    got = unpack_rows(out_words[rows], width)
+    want = oracle.edge_rows(img, 0, rows, img.shape[0], border=border, clauses=clauses)
+    return bool(np.array_equal(got, want))
+
+
+# ------------------------------------------------------------ workloads ----
+
+def headline(torch, em, tm, steps, warmup):
+    from synth import images, pack_rows, unpack_rows
+    import oracle
+    H = W = 8192
+    NB = 40
+    log("generating 8192x8192 glyph page (seed 2)")
+    img = images.glyph_page(H, W, seed=2)
+    words = pack_rows(img, 64)
+    src = words_tensor(torch, words)
+    ins = [src.clone() for _ in range(NB)]
+    outs = [torch.empty_like(src) for _ in range(NB)]
+    em.edge_masks(ins[0], outs[0], H, W)
+    torch.cuda.synchronize()
+    got = unpack_rows(outs[0].cpu().numpy().view(np.uint64), W)
+    exact = bool(np.array_equal(got, oracle.edge(img)))
+    log(f"headline parity vs oracle (whole image): {exact}")
+
+    def step(i):
+        em.edge_masks(ins[i % NB], outs[i % NB], H, W)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    ms = tm.per_call_ms(step, steps)
+    del ins, outs
+    torch.cuda.empty_cache()
+    return img, ms, exact
+
+
+def copy_ceiling(torch, em, tm, nbytes, nb, steps):
+    srcs = [torch.empty(nbytes // 8, dtype=torch.int64, device="cuda") for _ in range(nb)]
+    dsts = [torch.empty_like(s) for s in srcs]
+    for s in srcs:
+        s.fill_(1)
+
+    def step(i):
+        em.copy_bytes(srcs[i % nb], dsts[i % nb], nbytes)
+
+    for i in range(10):
+        step(i)
+    ms = tm.per_call_ms(step, steps)
+    del srcs, dsts
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def plain_512(torch, em, tm, steps):
+    from synth import images, pack_rows, unpack_rows
+    import oracle
+    img, k = images.strokes_image(512, 512, seed=1)
+    words = pack_rows(img, 32)
+    inp = words_tensor(torch, words)
+    out = torch.empty_like(inp)
+    em.edge_masks(inp, out, 512, 512)
+    torch.cuda.synchronize()
+    exact = bool(np.array_equal(unpack_rows(out.cpu().numpy().view(np.uint32), 512),
+                                oracle.edge(img)))
+    for _ in range(50):
+        em.edge_masks(inp, out, 512, 512)
+    ms = tm.per_call_ms(lambda i: em.edge_masks(inp, out, 512, 512), steps)
+    return {"workload": "plain, 512x512 strokes (seed 1, redraw k=%d), uint32" % k,
+            "gpx_s": round(512 * 512 / (ms * 1e-3) / 1e9, 2), "us_per_launch": round(ms * 1e3, 2),
+            "bit_exact": exact, "note": "latency-bound: 64 KiB per launch"}
+
+
+def plain_65536(torch, em, tm, steps):
+    from synth import images, pack_rows, unpack_rows
+    import oracle
+    H = W = 65536
+    log("building 65536x65536 page (8x8 tiles of an 8192^2 glyph page, seed 22)")
+    tile_img = images.glyph_page(8192, 8192, seed=22)
+    words = np.tile(pack_rows(tile_img, 64), (8, 8))
+    inp = words_tensor(torch, words)
+    del words
+    out = torch.empty_like(inp)
+    em.edge_masks(inp, out, H, W)
+    torch.cuda.synchronize()
+    # image row y is tile row y % 8192 repeated 8 times across
+    ok = True
+    for r in (0, 1, 8191, 8192, 30000, 65534, 65535):
+        lo, hi = max(0, r - 1), min(H, r + 2)
+        win = np.tile(np.stack([tile_img[y % 8192] for y in range(lo, hi)]), (1, 8))
+        want = oracle.edge(win)[r - lo]
+        got = unpack_rows(out[r:r + 1].cpu().numpy().view(np.uint64), W)[0]
+        ok &= bool(np.array_equal(got, want))
+    for _ in range(3):
+        em.edge_masks(inp, out, H, W)
+    ms = tm.per_call_ms(lambda i: em.edge_masks(inp, out, H, W), steps)
+    nbytes = 2 * H * (W // 64) * 8
+    del inp, out
+    torch.cuda.empty_cache()
+    return {"workload": "plain, 65536x65536 tiled glyph page (seed 22), uint64, 1 GiB per launch",
+            "gpx_s": round(H * W / (ms * 1e-3) / 1e9, 1), "ms_per_launch": round(ms, 4),
+            "roofline": roofline(nbytes, ms), "sampled_rows_bit_exact": ok}
+
+
+def full_16384(torch, em, tm, steps):
+    from synth import images, pack_rows, unpack_rows
+    import oracle
+    H = W = 16384
+    NB = 10
+    log("generating 16384x16384 skeleton page (seed 4)")
+    img = images.skeleton_page(H, W, seed=4)
+    words = pack_rows(img, 64)
+    src = words_tensor(torch, words)
+    ins = [src.clone() for _ in range(NB)]
+    outs = [torch.empty_like(src) for _ in range(NB)]
+    rows = np.array([0, 1, 2, 777, 8191, 8192, 12345, 16382, 16383])
+    em.edge_full(ins[0], outs[0], H, W)
+    torch.cuda.synchronize()
+    ok = check_rows(img, outs[0].cpu().numpy().view(np.uint64), W, rows, clauses=3)
+    em.edge_full(ins[0], outs[0], H, W, clause2_only=True)
+    torch.cuda.synchronize()
+    c2 = outs[0].cpu().numpy().view(np.uint64)
+    ok2 = check_rows(img, c2, W, rows, clauses=2)
+    n_c2 = int(sum(int(v).bit_count() for v in c2[rows].reshape(-1)))
+    for i in range(5):
+        em.edge_full(ins[i % NB], outs[i % NB], H, W)
+    ms = tm.per_call_ms(lambda i: em.edge_full(ins[i % NB], outs[i % NB], H, W), steps)
+    del ins, outs
+    torch.cuda.empty_cache()
+    nbytes = 2 * H * (W // 64) * 8
+    return {"workload": "full definition, 16384x16384 skeleton+stroke page (seed 4), uint64, "
+                        "10 rotating buffer pairs",
+            "gpx_s": round(H * W / (ms * 1e-3) / 1e9, 1), "ms_per_launch": round(ms, 4),
+            "roofline": roofline(nbytes, ms), "sampled_rows_bit_exact": ok and ok2,
+            "clause2_pixels_in_sample": n_c2}
+
+
+def batched_crops(torch, em, tm, steps):
+    from synth import images, pack_rows, unpack_rows
+    import oracle
+    from paper_1401_5245_amd import _abi
+    log("generating 4096 glyph crops (seed 3)")
+    crops = images.glyph_crops(4096, seed=3)
+    b = em.Batch([(pack_rows(c, 32), c.shape[1]) for c in crops], 32, "cuda")
+    g = b.graph()
+    g.launch()
+    torch.cuda.synchronize()
+    host = b.out.cpu().numpy().view(np.uint32)
+    exact = all(np.array_equal(unpack_rows(b.output_words(i, host), c.shape[1]), oracle.edge(c))
+                for i, c in enumerate(crops[:256]))
+    px = int(sum(c.size for c in crops))
+    for _ in range(10):
+        g.launch()
+    ms_graph = tm.per_call_ms(lambda i: g.launch(), steps)
+    ms_eager = tm.per_call_ms(lambda i: b.run(), steps)
+    # baseline: one edge_masks launch per crop, same arenas, one stream
+    lib = _abi.load()
+    base_in, base_out = b.inp.data_ptr(), b.out.data_ptr()
+    stream = int(torch.cuda.current_stream().cuda_stream)
+    calls = [(base_in + int(d["offset_words"]) * 4, base_out + int(d["offset_words"]) * 4,
+              int(d["height"]), int(d["width"]), int(d["stride_words"])) for d in b.table]
+
+    def per_image(_):
+        for (pi, po, h, w, s) in calls:
+            lib.edge_masks(pi, po, h, w, s, 32, 0, stream)
+
+    per_image(0)
+    ms_plain = tm.per_call_ms(per_image, max(3, steps // 50))
+    return {"workload": "batched, 4096 glyph crops H,W log-uniform [24,256] (seed 3), uint32, "
+                        "%.1f Mpx" % (px / 1e6),
+            "gpx_s_graph": round(px / (ms_graph * 1e-3) / 1e9, 1),
+            "gpx_s_eager": round(px / (ms_eager * 1e-3) / 1e9, 1),
+            "gpx_s_per_image_launches": round(px / (ms_plain * 1e-3) / 1e9, 2),
+            "speedup_vs_per_image": round(ms_plain / ms_graph, 1),
+            "us_graph": round(ms_graph * 1e3, 2), "cfg": b.kw["cfg"] or em.default_cfg(
+                0, 0, 32, batch=True),
+            "bit_exact_first_256": exact}
+
+
+def cpu_baseline(img, seconds):
+    import oracle
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.edge(img)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or reps >= 100:
+            break
+    gpx = img.size * reps / el / 1e9
+    return {"value": round(gpx, 4), "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} x the 8192x8192 headline image as bytes (packing excluded), "
+                      f"{el:.1f} s on one thread of {platform.processor() or 'the host'}"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    ensure_built()
+    import torch
+    import paper_1401_5245_amd as em
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    tm = Timer(torch)
+    img, ms, exact = headline(torch, em, tm, args.steps, args.warmup)
+    H = W = 8192
+    gpx = H * W / (ms * 1e-3) / 1e9
+    nbytes = 2 * H * (W // 64) * 8
+    res = {"metric": METRIC, "value": round(gpx, 1), "unit": "Gpixel/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+           "data": "synthetic",
+           "config": {"workload": "plain method (Edge(p) = NOT p AND (n2|n4|n6|n8)), one "
+                                  "8192x8192 binary glyph page (seed 2, ~19% black, 0.5% "
+                                  "salt-and-pepper), packed uint64 rows, white border, 40 "
+                                  "rotating buffer pairs",
+                      "pixels_per_step": H * W, "bytes_per_step": nbytes},
+           "roofline": roofline(nbytes, ms), "bit_exact": exact}
+    if not args.no_cpu and not args.headline_only:
+        log("timing the CPU oracle")
+        res["cpu_baseline"] = cpu_baseline(img, args.cpu_seconds)
+    if not args.headline_only:
+        extra = {}
+        log("copy ceiling")
+        extra["copy_ceiling_gbs_16MiB"] = round(copy_ceiling(torch, em, tm, 8 << 20, 40,
+                                                             args.steps), 1)
+        extra["copy_ceiling_gbs_1GiB"] = round(copy_ceiling(torch, em, tm, 512 << 20, 2, 20), 1)
+        res["roofline"]["frac_of_copy"] = round(res["roofline"]["achieved"] /
+                                                extra["copy_ceiling_gbs_16MiB"], 3)
+        log("config: plain 512^2")
+        extra["plain_512"] = plain_512(torch, em, tm, args.steps)
+        log("config: plain 65536^2")
+        extra["plain_65536"] = plain_65536(torch, em, tm, 20)
+        log("config: full 16384^2")
+        extra["full_16384"] = full_16384(torch, em, tm, 50)
+        log("config: batched crops")
+        extra["batched_4096"] = batched_crops(torch, em, tm, args.steps)
+        res["extra"] = extra
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * edge_masks.h - C ABI of libedgemask, a gfx950 (MI355X) library for edge
+ * detection of binary images by the method of masks (Sadeq, Wahdan, Mahdi,
+ * "Edge Detection of Binary Images Using the Method of Masks", 2000).
+ *
+ * WHAT IS COMPUTED
+ *   An image is a monochrome bit-stream, one bit per pixel, 0 = black and
+ *   1 = white (paper, section 2). A pixel p is an edge point when
+ *       Edge(p) = (NOT p) AND (n2 OR n4 OR n6 OR n8)
+ *   (Boolean function of section 1), with n2, n4, n6, n8 the up, left, down
+ *   and right neighbours of the numbering of Fig. 1:
+ *        n3 n2 n1
+ *        n4  P n8
+ *        n5 n6 n7
+ *   The paper gets there in three stages: the mask is the negative image
+ *   (section 3); each of the four fundamental edges is the image shifted by
+ *   one pixel in one direction ANDed with the mask (section 4); the edge is
+ *   the OR of the four (section 5). The library fuses the three stages into
+ *   one pass over the packed words: by distributivity the OR of the four
+ *   masked shifts equals the mask ANDed with the OR of the four shifts.
+ *
+ *   The full definition of section 1 also counts as an edge point a black
+ *   pixel with at most one black 8-neighbour ("full mode"). Such a pixel
+ *   always has at least three white 4-neighbours, so the full-mode output
+ *   equals the plain output bit for bit; EDGE_FLAG_CLAUSE2_ONLY exposes the
+ *   second clause on its own.
+ *
+ * PACKED LAYOUT (every entry point)
+ *   Rows of B-bit words, B = word_bits = 32 or 64, little-endian, LSB first:
+ *   pixel (x, y) is bit (x mod B) of word (y * stride_words + x / B).
+ *   A row has Wd = ceil(width / B) valid words; stride_words >= Wd.
+ *   - Input bits at x >= width inside the valid words are ignored.
+ *   - Output bits at x >= width inside the valid words are written as 0.
+ *   - Stride words Wd .. stride_words-1 are neither read nor written.
+ *   The byte layout of a row is the same for B = 32 and B = 64.
+ *
+ * OUTSIDE THE IMAGE
+ *   The paper does not say what a shifted block brings in at the frame.
+ *   `border` chooses: EDGE_BORDER_WHITE (default; out-of-image pixels are
+ *   white, so black pixels on the frame are edge points) or
+ *   EDGE_BORDER_BLACK. Both clauses use the same convention.
+ *
+ * CALLING RULES
+ *   - All device pointers are caller-owned device memory. The library
+ *     allocates no device memory; graph handles are the only objects it owns.
+ *   - Every call is asynchronous on `hip_stream` (a hipStream_t; NULL = the
+ *     null stream) and returns once the work is enqueued. Inputs must stay
+ *     valid and unmodified until the stream reaches the work.
+ *   - Argument errors are returned before any HIP call is made.
+ *   - height == 0 or width == 0 is a no-op returning EDGE_OK.
+ *   - In-place operation is not supported: overlapping input and output
+ *     byte ranges return EDGE_ERR_ALIAS.
+ *   - Pointers must be aligned to B/8 bytes (EDGE_ERR_ALIGN otherwise).
+ *     16-byte alignment of the pointers and of the row pitch enables 128-bit
+ *     loads and stores.
+ *   - Functions are reentrant and keep no mutable global state apart from a
+ *     per-device compute-unit count cached on first use.
+ */
+#ifndef EDGE_MASKS_H
+#define EDGE_MASKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EDGE_MASKS_ABI_VERSION 1
+
+/* Status codes returned by every int-returning entry point. */
+enum {
+    EDGE_OK = 0,
+    EDGE_ERR_INVALID = -1,     /* bad size, stride, enum, flag or descriptor */
+    EDGE_ERR_ALIGN = -2,       /* pointer not aligned to the word size */
+    EDGE_ERR_ALIAS = -3,       /* input and output byte ranges overlap */
+    EDGE_ERR_HIP = -4,         /* a HIP call failed; see edge_last_hip_error() */
+    EDGE_ERR_WORKSPACE = -5,   /* workspace missing, too small or misaligned */
+    EDGE_ERR_UNSUPPORTED = -6  /* launch configuration outside what is built */
+};
+
+/* Colour of pixels outside the image. */
+enum { EDGE_BORDER_WHITE = 0, EDGE_BORDER_BLACK = 1 };
+
+/* Which definition of section 1: clause 1 only, or clause 1 OR clause 2. */
+enum { EDGE_MODE_MASKS = 0, EDGE_MODE_FULL = 1 };
+
+/* Flags. CLAUSE2_ONLY (full mode only): output the black pixels with at
+ * most one black 8-neighbour, without clause 1. INVERT_OUT: the display
+ * polarity of section 5 (edge pixels 0, others 1); padding bits stay 0. */
+enum { EDGE_FLAG_CLAUSE2_ONLY = 1u << 0, EDGE_FLAG_INVERT_OUT = 1u << 1 };
+
+/* One image of a batch. Offsets and strides count B-bit words from the
+ * start of the arena; in and out arenas share the same descriptors. */
+typedef struct edge_image_desc {
+    int64_t offset_words;
+    int32_t height;
+    int32_t width;
+    int64_t stride_words;
+} edge_image_desc;
+
+/* Launch configuration (all fields > 0; NULL selects the built-in choice).
+ *   vec_words       32-bit words per lane for wide rows: 1, 2 or 4.
+ *   rows_per_tile   rows one wavefront walks down per work unit, 1..1024.
+ *   waves_per_block wavefronts per workgroup: 1, 2, 4 or 8.
+ *   blocks_per_cu   persistent workgroups per compute unit (batch only),
+ *                   1..32; ignored by the single-image calls. */
+typedef struct edge_launch_cfg {
+    int32_t vec_words;
+    int32_t rows_per_tile;
+    int32_t waves_per_block;
+    int32_t blocks_per_cu;
+} edge_launch_cfg;
+
+/* Plain method (Boolean function Edge(p), section 1; stages of sections
+ * 3-5). `in`, `out`: device pointers to height rows of stride_words words.
+ * Returns EDGE_OK or an error status. */
+int edge_masks(const void* in, void* out, int64_t height, int64_t width,
+               int64_t stride_words, int word_bits, int border, void* hip_stream);
+
+/* Full definition of an edge point (section 1, both clauses). `flags` may
+ * hold EDGE_FLAG_CLAUSE2_ONLY and EDGE_FLAG_INVERT_OUT. */
+int edge_full(const void* in, void* out, int64_t height, int64_t width,
+              int64_t stride_words, int word_bits, int border, uint32_t flags,
+              void* hip_stream);
+
+/* Single image with an explicit mode, flags and launch configuration
+ * (cfg == NULL: built-in choice). Same computation as edge_masks /
+ * edge_full; used by the autotuner to time candidate configurations.
+ * EDGE_FLAG_CLAUSE2_ONLY requires mode == EDGE_MODE_FULL. */
+int edge_image_launch(const void* in, void* out, int64_t height, int64_t width,
+                      int64_t stride_words, int word_bits, int border, int mode,
+                      uint32_t flags, const edge_launch_cfg* cfg, void* hip_stream);
+
+/* Built-in launch configuration for an image shape (batch != 0: for the
+ * persistent batch kernel). Returns EDGE_OK and fills *cfg_out. */
+int edge_default_cfg(int64_t height, int64_t width, int word_bits, int mode,
+                     int batch, edge_launch_cfg* cfg_out);
+
+/* Bytes of device workspace edge_batch needs for n_images descriptors.
+ * Returns a negative status for n_images < 0. */
+int64_t edge_batch_workspace_bytes(int32_t n_images);
+
+/* Host-side check of a descriptor table (host memory) against arenas of
+ * arena_words words: sizes >= 0, stride >= Wd, every image inside the
+ * arena. Returns EDGE_OK or EDGE_ERR_INVALID. */
+int edge_batch_check(const edge_image_desc* table_host, int32_t n_images,
+                     int64_t arena_words, int word_bits);
+
+/* Many independent images in one persistent launch (each image as in
+ * edge_masks / edge_full; no bits cross between images).
+ *   in_arena, out_arena: device arenas of arena_words B-bit words each.
+ *   table_dev: device array of n_images descriptors (read by the device
+ *     when the stream reaches the work, so it may be rewritten in place
+ *     between graph replays).
+ *   workspace_dev: device scratch of >= edge_batch_workspace_bytes(n)
+ *     bytes, 256-byte aligned, owned by the caller; overwritten each call.
+ *   mode, flags: as edge_image_launch. cfg: NULL = built-in choice.
+ * A descriptor that fails the checks of edge_batch_check is skipped on the
+ * device (its output untouched) and flagged in the workspace; callers
+ * should run edge_batch_check on the host copy first. Two calls that share
+ * a workspace must not overlap in time. */
+int edge_batch(const void* in_arena, void* out_arena, int64_t arena_words,
+               const edge_image_desc* table_dev, int32_t n_images, int word_bits,
+               int border, int mode, uint32_t flags, const edge_launch_cfg* cfg,
+               void* workspace_dev, int64_t workspace_bytes, void* hip_stream);
+
+/* Capture the work of one edge_batch call (same arguments) into an
+ * instantiated HIP graph. *graph_out receives an opaque handle. */
+int edge_batch_graph_create(const void* in_arena, void* out_arena, int64_t arena_words,
+                            const edge_image_desc* table_dev, int32_t n_images,
+                            int word_bits, int border, int mode, uint32_t flags,
+                            const edge_launch_cfg* cfg, void* workspace_dev,
+                            int64_t workspace_bytes, void** graph_out);
+
+/* Replay a captured batch on `hip_stream`. */
+int edge_graph_launch(void* graph, void* hip_stream);
+
+/* Free a graph handle (NULL is a no-op). */
+int edge_graph_destroy(void* graph);
+
+/* Plain device copy of n_bytes (multiple of 16, 16-byte aligned pointers,
+ * no overlap): the bandwidth ceiling that the edge kernels are compared to. */
+int edge_copy_bytes(const void* in, void* out, int64_t n_bytes, void* hip_stream);
+
+/* Text for a status code (static storage). */
+const char* edge_status_string(int status);
+
+/* hipError_t of the last EDGE_ERR_HIP on the calling thread (0 if none). */
+int edge_last_hip_error(void);
+
+/* EDGE_MASKS_ABI_VERSION of the built library. */
+int edge_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EDGE_MASKS_H */

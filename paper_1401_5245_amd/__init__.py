@@ -1,0 +1,117 @@
+"""MI355X (gfx950) edge detection of binary images by the method of masks.
+
+Thin Python binding of libedgemask (C ABI in include/edge_masks.h). Every
+step of the computation runs in the library's HIP kernels; this module only
+checks tensors and passes device pointers, sizes and the current HIP stream.
+PyTorch provides device memory and streams.
+
+Images are packed rows of 32- or 64-bit words (pixel x of row y is bit
+x % B of word y * stride + x // B, black = 0, white = 1), held in torch
+tensors of dtype int32/uint32 (B = 32) or int64/uint64 (B = 64).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._abi import (EDGE_BORDER_BLACK, EDGE_BORDER_WHITE, EDGE_FLAG_CLAUSE2_ONLY,  # noqa: F401
+                   EDGE_FLAG_INVERT_OUT, EDGE_MODE_FULL, EDGE_MODE_MASKS, EdgeError,
+                   EdgeImageDesc, EdgeLaunchCfg, check, load)
+
+_lib = load()
+
+BORDERS = {"white": EDGE_BORDER_WHITE, "black": EDGE_BORDER_BLACK}
+MODES = {"masks": EDGE_MODE_MASKS, "full": EDGE_MODE_FULL}
+_WORD_DTYPES = {torch.int32: 32, torch.int64: 64}
+for _name, _bits in (("uint32", 32), ("uint64", 64)):
+    if hasattr(torch, _name):
+        _WORD_DTYPES[getattr(torch, _name)] = _bits
+
+
+def word_bits_of(t: torch.Tensor) -> int:
+    try:
+        return _WORD_DTYPES[t.dtype]
+    except KeyError:
+        raise TypeError(f"packed words must be 32- or 64-bit integers, got {t.dtype}") from None
+
+
+def stream_handle(stream=None) -> int:
+    """HIP stream handle of `stream` (default: torch's current stream)."""
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _image_args(inp: torch.Tensor, out: torch.Tensor, height: int, width: int,
+                stride_words):
+    if not (inp.is_cuda and out.is_cuda):
+        raise ValueError("input and output must be device tensors")
+    if inp.dtype != out.dtype:
+        raise TypeError("input and output must have the same word type")
+    if not (inp.is_contiguous() and out.is_contiguous()):
+        raise ValueError("input and output must be contiguous")
+    wb = word_bits_of(inp)
+    if stride_words is None:
+        if inp.dim() != 2:
+            raise ValueError("pass stride_words for a tensor that is not (H, stride)")
+        stride_words = inp.shape[1]
+    need = (height - 1) * stride_words + -(-width // wb) if height and width else 0
+    if inp.numel() < need or out.numel() < need:
+        raise ValueError(f"tensors hold fewer than the {need} words the image spans")
+    return wb, int(stride_words)
+
+
+def _cfg_ptr(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, dict):
+        cfg = EdgeLaunchCfg.from_dict(cfg)
+    return ctypes.byref(cfg)
+
+
+def edge_masks(inp: torch.Tensor, out: torch.Tensor, height: int, width: int, *,
+               border: str = "white", stride_words=None, stream=None) -> torch.Tensor:
+    """Plain method: out = NOT(p) AND (n2 OR n4 OR n6 OR n8) for every pixel."""
+    wb, s = _image_args(inp, out, height, width, stride_words)
+    check(_lib.edge_masks(inp.data_ptr(), out.data_ptr(), height, width, s, wb, BORDERS[border],
+                          stream_handle(stream)))
+    return out
+
+
+def edge_full(inp: torch.Tensor, out: torch.Tensor, height: int, width: int, *,
+              border: str = "white", clause2_only: bool = False, invert: bool = False,
+              stride_words=None, stream=None) -> torch.Tensor:
+    """Full definition: clause 1 OR black pixels with <= 1 black 8-neighbour."""
+    wb, s = _image_args(inp, out, height, width, stride_words)
+    flags = (EDGE_FLAG_CLAUSE2_ONLY if clause2_only else 0) | (EDGE_FLAG_INVERT_OUT if invert else 0)
+    check(_lib.edge_full(inp.data_ptr(), out.data_ptr(), height, width, s, wb, BORDERS[border],
+                         flags, stream_handle(stream)))
+    return out
+
+
+def edge_image(inp: torch.Tensor, out: torch.Tensor, height: int, width: int, *,
+               mode: str = "masks", border: str = "white", clause2_only: bool = False,
+               invert: bool = False, cfg=None, stride_words=None, stream=None) -> torch.Tensor:
+    """Single image with explicit mode, flags and launch configuration."""
+    wb, s = _image_args(inp, out, height, width, stride_words)
+    flags = (EDGE_FLAG_CLAUSE2_ONLY if clause2_only else 0) | (EDGE_FLAG_INVERT_OUT if invert else 0)
+    check(_lib.edge_image_launch(inp.data_ptr(), out.data_ptr(), height, width, s, wb,
+                                 BORDERS[border], MODES[mode], flags, _cfg_ptr(cfg),
+                                 stream_handle(stream)))
+    return out
+
+
+def default_cfg(height: int, width: int, word_bits: int, mode: str = "masks",
+                batch: bool = False) -> dict:
+    c = EdgeLaunchCfg()
+    check(_lib.edge_default_cfg(height, width, word_bits, MODES[mode], int(batch), ctypes.byref(c)))
+    return c.as_dict()
+
+
+def copy_bytes(src: torch.Tensor, dst: torch.Tensor, n_bytes: int, stream=None) -> None:
+    """Plain 128-bit device copy (the bandwidth reference for the kernels)."""
+    check(_lib.edge_copy_bytes(src.data_ptr(), dst.data_ptr(), n_bytes, stream_handle(stream)))
+
+
+from .batch import (Batch, BatchGraph, batch_workspace_bytes, edge_batch,  # noqa: E402,F401
+                    pack_arena)

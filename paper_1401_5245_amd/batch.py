@@ -1,0 +1,185 @@
+"""Many images in one persistent launch: arenas, descriptor tables, graphs.
+
+A batch is two device arenas of packed words (input and output, same
+layout), a device table of ``edge_image_desc`` records (offset, height,
+width, stride; offsets and strides in words) and a small device workspace
+the library writes its work plan into. ``edge_batch`` enqueues the planner
+and the persistent kernel; ``BatchGraph`` captures the same work once in a
+HIP graph and replays it.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._abi import (EDGE_FLAG_CLAUSE2_ONLY, EDGE_FLAG_INVERT_OUT, EdgeImageDesc, EdgeLaunchCfg,
+                   check, load)
+
+_lib = load()
+
+DESC_DTYPE = np.dtype([("offset_words", "<i8"), ("height", "<i4"), ("width", "<i4"),
+                       ("stride_words", "<i8")])
+assert DESC_DTYPE.itemsize == ctypes.sizeof(EdgeImageDesc)
+
+_BORDERS = {"white": 0, "black": 1}
+_MODES = {"masks": 0, "full": 1}
+_NP_WORDS = {32: np.uint32, 64: np.uint64}
+_TORCH_WORDS = {32: torch.int32, 64: torch.int64}
+
+
+def _flags(clause2_only: bool, invert: bool) -> int:
+    return (EDGE_FLAG_CLAUSE2_ONLY if clause2_only else 0) | (EDGE_FLAG_INVERT_OUT if invert else 0)
+
+
+def _cfg_ptr(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, dict):
+        cfg = EdgeLaunchCfg.from_dict(cfg)
+    return ctypes.byref(cfg)
+
+
+def _word_bits(t: torch.Tensor) -> int:
+    from . import word_bits_of
+    return word_bits_of(t)
+
+
+def batch_workspace_bytes(n_images: int) -> int:
+    v = int(_lib.edge_batch_workspace_bytes(n_images))
+    if v < 0:
+        check(v)
+    return v
+
+
+def pack_arena(images, word_bits: int, align_words: int | None = None):
+    """Concatenate packed images into one arena.
+
+    ``images``: sequence of ``(words, width)`` with ``words`` an (H, S)
+    array of packed rows. Each image starts at a multiple of
+    ``align_words`` (default: 16 bytes). Returns ``(arena, table)``: a 1-D
+    word array and a structured array of descriptors.
+    """
+    if align_words is None:
+        align_words = 128 // word_bits
+    n = len(images)
+    table = np.zeros(n, dtype=DESC_DTYPE)
+    off = 0
+    for i, (w, width) in enumerate(images):
+        H, S = w.shape
+        off = -(-off // align_words) * align_words
+        table[i] = (off, H, width, S)
+        off += H * S
+    total = -(-off // align_words) * align_words
+    arena = np.zeros(max(total, align_words), dtype=_NP_WORDS[word_bits])
+    for i, (w, _) in enumerate(images):
+        o = int(table[i]["offset_words"])
+        arena[o:o + w.size] = w.reshape(-1)
+    return arena, table
+
+
+def check_table(table: np.ndarray, arena_words: int, word_bits: int) -> None:
+    """Host-side validation of a descriptor table (raises EdgeError)."""
+    t = np.ascontiguousarray(table, dtype=DESC_DTYPE)
+    check(_lib.edge_batch_check(t.ctypes.data if len(t) else None, len(t), arena_words, word_bits))
+
+
+def table_to_device(table: np.ndarray, device="cuda") -> torch.Tensor:
+    t = np.ascontiguousarray(table, dtype=DESC_DTYPE)
+    return torch.from_numpy(t.view(np.int64).reshape(-1, 3).copy()).to(device)
+
+
+def edge_batch(in_arena: torch.Tensor, out_arena: torch.Tensor, table_dev: torch.Tensor,
+               n_images: int, workspace: torch.Tensor, *, border: str = "white",
+               mode: str = "masks", clause2_only: bool = False, invert: bool = False, cfg=None,
+               stream=None) -> None:
+    """Enqueue one batched launch (planner + persistent kernel)."""
+    from . import stream_handle
+    wb = _word_bits(in_arena)
+    if out_arena.dtype != in_arena.dtype or out_arena.numel() != in_arena.numel():
+        raise ValueError("input and output arenas must match in type and size")
+    check(_lib.edge_batch(in_arena.data_ptr(), out_arena.data_ptr(), in_arena.numel(),
+                          table_dev.data_ptr(), n_images, wb, _BORDERS[border], _MODES[mode],
+                          _flags(clause2_only, invert), _cfg_ptr(cfg), workspace.data_ptr(),
+                          workspace.numel() * workspace.element_size(), stream_handle(stream)))
+
+
+class BatchGraph:
+    """One batched launch captured in a HIP graph; replay with launch().
+
+    The graph reads the descriptor table when it runs, so the table's
+    contents (not its size or address) may be rewritten between replays.
+    The tensors passed in are kept alive by this object.
+    """
+
+    def __init__(self, in_arena, out_arena, table_dev, n_images, workspace, *,
+                 border="white", mode="masks", clause2_only=False, invert=False, cfg=None):
+        wb = _word_bits(in_arena)
+        self._keep = (in_arena, out_arena, table_dev, workspace)
+        h = ctypes.c_void_p()
+        check(_lib.edge_batch_graph_create(
+            in_arena.data_ptr(), out_arena.data_ptr(), in_arena.numel(), table_dev.data_ptr(),
+            n_images, wb, _BORDERS[border], _MODES[mode], _flags(clause2_only, invert),
+            _cfg_ptr(cfg), workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+            ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        from . import stream_handle
+        if not self._h:
+            raise RuntimeError("graph destroyed")
+        check(_lib.edge_graph_launch(self._h, stream_handle(stream)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            check(_lib.edge_graph_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Packed images resident in device arenas, ready to launch.
+
+    ``images``: sequence of ``(words, width)`` (see pack_arena).
+    """
+
+    def __init__(self, images, word_bits: int, device="cuda", *, border="white",
+                 mode="masks", clause2_only=False, invert=False, cfg=None):
+        arena, table = pack_arena(images, word_bits)
+        check_table(table, arena.size, word_bits)
+        self.word_bits = word_bits
+        self.table = table
+        self.n = len(table)
+        self.kw = dict(border=border, mode=mode, clause2_only=clause2_only, invert=invert,
+                       cfg=cfg)
+        host = torch.from_numpy(arena.view(np.int64 if word_bits == 64 else np.int32))
+        self.inp = host.to(device)
+        self.out = torch.zeros_like(self.inp)
+        self.table_dev = table_to_device(table, device)
+        nb = batch_workspace_bytes(self.n)
+        self.workspace = torch.zeros(-(-nb // 8), dtype=torch.int64, device=device)
+        self._graph = None
+
+    def run(self, stream=None) -> None:
+        edge_batch(self.inp, self.out, self.table_dev, self.n, self.workspace, stream=stream,
+                   **self.kw)
+
+    def graph(self) -> BatchGraph:
+        if self._graph is None:
+            self._graph = BatchGraph(self.inp, self.out, self.table_dev, self.n, self.workspace,
+                                     **self.kw)
+        return self._graph
+
+    def output_words(self, i: int, out_host: np.ndarray | None = None) -> np.ndarray:
+        """Packed output rows (H, S) of image i (copies the arena if needed)."""
+        if out_host is None:
+            out_host = self.out.cpu().numpy().view(_NP_WORDS[self.word_bits])
+        d = self.table[i]
+        o, H, S = int(d["offset_words"]), int(d["height"]), int(d["stride_words"])
+        return out_host[o:o + H * S].reshape(H, S)

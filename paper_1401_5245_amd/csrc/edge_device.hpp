@@ -1,0 +1,383 @@
+// edge_device.hpp - gfx950 device code of libedgemask: the fused method of
+// masks on packed binary rows.
+//
+// The paper's three stages (mask = negative image, section 3; four
+// fundamental edges = image shifted one pixel ANDed with the mask, section 4;
+// edge = OR of the four, section 5) are fused into one pass. Per 32-bit word
+// c of a row, with u and d the words above and below and w, e the image
+// shifted by one pixel to the right and to the left:
+//     edge = ~c & (u | d | w | e)
+// which is the Boolean function Edge(p) of section 1 for 32 pixels at once
+// (distributivity turns the OR of four masked shifts into one mask).
+//
+// Layout: rows of 32-bit words, LSB first (pixel x is bit x % 32 of word
+// x / 32). 64-bit words have the same byte layout, so the host passes every
+// image as 32-bit words with the row length rounded up to whole 64-bit words.
+// Bits at x >= width take the border colour on input and are 0 on output.
+//
+// Work decomposition: one wavefront (64 lanes) per work unit.
+//   - strip unit: 64 * VW consecutive words of each of `rows` consecutive
+//     rows; each lane owns VW words and walks down the rows keeping the rows
+//     above and below in registers, so every input word is loaded once per
+//     strip (plus one halo row above and below). West/east carries between
+//     lanes move with DPP wavefront shifts; the words just outside the
+//     wavefront's span are loaded by lanes 0 and 63.
+//   - narrow unit (rows of <= 32 words): several whole rows side by side in
+//     one wavefront, one word per lane, rows above and below read directly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace edgek {
+
+constexpr int kWave = 64;
+constexpr int kPrefetch = 4;   // rows each lane keeps in flight in a strip
+constexpr int kNarrowSteps = 4; // narrow-unit steps loaded ahead of use
+constexpr int kNarrowMaxWords = 32;
+
+enum { kModePlain = 0, kModeFull = 1, kModeClause2 = 2 };
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// One image in 32-bit word units.
+struct Geom {
+    const uint32_t* in;
+    uint32_t* out;
+    int64_t stride;   // words between rows
+    int32_t height;   // rows
+    int32_t width;    // pixels per row
+    int32_t wd;       // words per row the kernels touch (whole B-bit words)
+};
+
+// ------------------------------------------------------------ word helpers --
+
+// Bits of word j that hold pixels x < width.
+__device__ __forceinline__ uint32_t valid_bits(int j, int32_t width) {
+    const int v = width - 32 * j;
+    if (v >= 32) return 0xffffffffu;
+    if (v <= 0) return 0u;
+    return (1u << (uint32_t)v) - 1u;
+}
+
+// Image shifted right by one pixel (section 4): bit x of the result holds
+// pixel x - 1, the left neighbour n4 of Fig. 1. `prev` is the word before c.
+__device__ __forceinline__ uint32_t west_of(uint32_t c, uint32_t prev) {
+    return __builtin_amdgcn_alignbit(c, prev, 31);
+}
+
+// Image shifted left by one pixel: bit x holds pixel x + 1, neighbour n8.
+__device__ __forceinline__ uint32_t east_of(uint32_t c, uint32_t next) {
+    return __builtin_amdgcn_alignbit(next, c, 1);
+}
+
+// Lane i receives v of lane i - 1; lane 0 receives `fill` (DPP wave_shr:1).
+__device__ __forceinline__ uint32_t from_lower_lane(uint32_t v, uint32_t fill) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x138, 0xf, 0xf, false);
+}
+
+// Lane i receives v of lane i + 1; lane 63 receives `fill` (DPP wave_shl:1).
+__device__ __forceinline__ uint32_t from_upper_lane(uint32_t v, uint32_t fill) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x130, 0xf, 0xf, false);
+}
+
+// Second clause of the definition in section 1, bit-sliced over 32 pixels:
+// bit x is 1 when at most one of the eight neighbour words has a 0 (black)
+// at bit x. `none` tracks "no black so far", `one` "at most one so far".
+__device__ __forceinline__ uint32_t at_most_one_black(uint32_t a1, uint32_t a2, uint32_t a3,
+                                                      uint32_t a4, uint32_t a5, uint32_t a6,
+                                                      uint32_t a7, uint32_t a8) {
+    uint32_t none = a1 & a2;
+    uint32_t one = a1 | a2;
+    one = (one & a3) | none; none &= a3;
+    one = (one & a4) | none; none &= a4;
+    one = (one & a5) | none; none &= a5;
+    one = (one & a6) | none; none &= a6;
+    one = (one & a7) | none; none &= a7;
+    one = (one & a8) | none;
+    return one;
+}
+
+// Output word for pixel word c with its eight neighbour words (Fig. 1
+// numbering: n1 NE, n2 N, n3 NW, n4 W, n5 SW, n6 S, n7 SE, n8 E).
+template <int MODE>
+__device__ __forceinline__ uint32_t edge_word(uint32_t c, uint32_t n1, uint32_t n2, uint32_t n3,
+                                              uint32_t n4, uint32_t n5, uint32_t n6, uint32_t n7,
+                                              uint32_t n8) {
+    const uint32_t white4 = n2 | n4 | n6 | n8;                 // section 1, Edge(p)
+    if constexpr (MODE == kModePlain) {
+        return ~c & white4;
+    } else {
+        const uint32_t few = at_most_one_black(n1, n2, n3, n4, n5, n6, n7, n8);
+        if constexpr (MODE == kModeFull) return ~c & (white4 | few);
+        else return ~c & few;
+    }
+}
+
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Spread consecutive workgroups over the eight XCDs in contiguous ranges:
+// the dispatcher sends workgroup b to XCD b % 8, so logical block order
+// b' keeps neighbouring tiles (which share halo rows) in one XCD's L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+    constexpr uint32_t X = 8;
+    const uint32_t xcd = b % X, idx = b / X, q = nb / X, rem = nb % X;
+    return xcd < rem ? xcd * (q + 1) + idx : rem * (q + 1) + (xcd - rem) * q + idx;
+}
+
+template <int VW>
+__device__ __forceinline__ void load_words(const uint32_t* p, uint32_t (&w)[VW]) {
+    if constexpr (VW == 4) {
+        const u32x4 v = *reinterpret_cast<const u32x4*>(p);
+        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    } else if constexpr (VW == 2) {
+        const u32x2 v = *reinterpret_cast<const u32x2*>(p);
+        w[0] = v.x; w[1] = v.y;
+    } else {
+        w[0] = *p;
+    }
+}
+
+template <int VW>
+__device__ __forceinline__ void store_words(uint32_t* p, const uint32_t (&w)[VW]) {
+    if constexpr (VW == 4) {
+        u32x4 v; v.x = w[0]; v.y = w[1]; v.z = w[2]; v.w = w[3];
+        *reinterpret_cast<u32x4*>(p) = v;
+    } else if constexpr (VW == 2) {
+        u32x2 v; v.x = w[0]; v.y = w[1];
+        *reinterpret_cast<u32x2*>(p) = v;
+    } else {
+        *p = w[0];
+    }
+}
+
+// --------------------------------------------------------------- strips ----
+
+// Rows [y0, y1) of words [j0, j0 + 64*VW) of image g, by the calling
+// wavefront (all 64 lanes active; every branch below is wave-uniform).
+// WHOLE: the span lies inside the row, so each lane moves its VW words with
+// one vector load and store; otherwise (the row's last chunk) each word is
+// loaded from a clamped address and stored only when it is inside the row.
+// `bw` is the border word (all ones for a white border, zero for black).
+//
+// Each lane keeps kPrefetch rows in flight in the ring q[]: the slot of the
+// row just consumed is refilled with the row kPrefetch rows further down.
+// Loads never branch: rows past y1 re-read row y1 (an L1 hit) and rows
+// outside the image are clamped into it and replaced by the border after
+// the load, so the hardware's in-order load counter waits exactly for the
+// row being consumed.
+template <int VW, int MODE, bool WHOLE>
+__device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1, uint32_t bw,
+                                           bool invert) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int jl = j0 + lane * VW;
+
+    uint32_t vm[VW], om[VW];
+    int jw[VW];
+    bool inrow[VW];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+        vm[k] = valid_bits(jl + k, g.width);
+        om[k] = bw & ~vm[k];
+        inrow[k] = jl + k < g.wd;
+        jw[k] = inrow[k] ? jl + k : j0;
+    }
+
+    // Words just outside the wavefront's span: lane 0 needs the word on the
+    // left, lane 63 the word on the right. Other lanes load a harmless word.
+    const int je = lane == 0 ? j0 - 1 : j0 + kWave * VW;
+    const bool has_e = (lane == 0 && j0 > 0) || (lane == kWave - 1 && je < g.wd);
+    const int je_load = has_e ? je : j0;
+    const uint32_t vme = valid_bits(je, g.width), ome = bw & ~vme;
+
+    struct Raw { uint32_t w[VW]; uint32_t e; };
+    struct Row { uint32_t c[VW], w[VW], e[VW]; };
+
+    auto load_raw = [&](int y) {
+        const int yc = y < 0 ? 0 : (y >= g.height ? g.height - 1 : y);
+        const uint32_t* rp = g.in + (int64_t)yc * g.stride;
+        Raw r;
+        if constexpr (WHOLE) {
+            load_words<VW>(rp + jl, r.w);
+        } else {
+#pragma unroll
+            for (int k = 0; k < VW; ++k) r.w[k] = rp[jw[k]];
+        }
+        r.e = rp[je_load];
+        return r;
+    };
+
+    // Pad bits take the border colour, rows outside the image become border
+    // rows; then the row shifted right (west neighbours, n4) and shifted
+    // left (east neighbours, n8) are formed with funnel shifts, the carry
+    // words crossing lanes by DPP.
+    auto shift_row = [&](const Raw& r, int y) {
+        const bool inside = (unsigned)y < (unsigned)g.height;
+        Row o;
+#pragma unroll
+        for (int k = 0; k < VW; ++k) o.c[k] = inside ? ((r.w[k] & vm[k]) | om[k]) : bw;
+        const uint32_t e = (inside && has_e) ? ((r.e & vme) | ome) : bw;
+        const uint32_t left = from_lower_lane(o.c[VW - 1], e);
+        const uint32_t right = from_upper_lane(o.c[0], e);
+#pragma unroll
+        for (int k = 0; k < VW; ++k) {
+            o.w[k] = west_of(o.c[k], k > 0 ? o.c[k - 1] : left);
+            o.e[k] = east_of(o.c[k], k + 1 < VW ? o.c[k + 1] : right);
+        }
+        return o;
+    };
+
+    auto emit = [&](int y, const Row& up, const Row& cur, const Row& dn) {
+        uint32_t res[VW];
+#pragma unroll
+        for (int k = 0; k < VW; ++k) {
+            const uint32_t v = edge_word<MODE>(cur.c[k], up.e[k], up.c[k], up.w[k], cur.w[k],
+                                               dn.w[k], dn.c[k], dn.e[k], cur.e[k]) & vm[k];
+            res[k] = invert ? (v ^ vm[k]) : v;
+        }
+        uint32_t* op = g.out + (int64_t)y * g.stride;
+        if constexpr (WHOLE) {
+            store_words<VW>(op + jl, res);
+        } else {
+#pragma unroll
+            for (int k = 0; k < VW; ++k)
+                if (inrow[k]) op[jl + k] = res[k];
+        }
+    };
+
+    const Raw ra = load_raw(y0 - 1);
+    const Raw rb = load_raw(y0);
+    Raw q[kPrefetch];
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) q[u] = load_raw(min(y0 + 1 + u, y1));
+    Row up = shift_row(ra, y0 - 1);
+    Row cur = shift_row(rb, y0);
+    int r = y0;
+    for (; r + kPrefetch <= y1; r += kPrefetch) {   // whole groups
+#pragma unroll
+        for (int u = 0; u < kPrefetch; ++u) {
+            const int y = r + u;
+            const Row dn = shift_row(q[u], y + 1);
+            q[u] = load_raw(min(y + 1 + kPrefetch, y1));
+            emit(y, up, cur, dn);
+            up = cur;
+            cur = dn;
+            // Keep each row's work in its own slot of the schedule; hoisting
+            // a later row's arithmetic would make the wavefront wait for
+            // every load in flight.
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u + 1 < kPrefetch; ++u) {        // last partial group
+        const int y = r + u;
+        if (y < y1) {
+            const Row dn = shift_row(q[u], y + 1);
+            emit(y, up, cur, dn);
+            up = cur;
+            cur = dn;
+        }
+    }
+}
+
+template <int VW, int MODE>
+__device__ __forceinline__ void strip_unit(const Geom& g, int j0, int y0, int y1, uint32_t bw,
+                                           bool invert) {
+    if (j0 + kWave * VW <= g.wd) strip_body<VW, MODE, true>(g, j0, y0, y1, bw, invert);
+    else strip_body<VW, MODE, false>(g, j0, y0, y1, bw, invert);
+}
+
+// --------------------------------------------------------- narrow units ----
+
+// Rows [ya, yb) of an image whose rows have g.wd <= 32 words: 64 / wd rows
+// side by side per wavefront step, one word per lane, kNarrowSteps steps
+// loaded before any is used. Lanes past the last row load a safe word and
+// store nothing.
+template <int MODE>
+__device__ __forceinline__ void narrow_unit(const Geom& g, int ya, int yb, uint32_t bw,
+                                            bool invert) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wd = g.wd;
+    const int grp = kWave / wd;
+    const int q = lane / wd;
+    const bool lane_used = q < grp;
+    const int j = lane_used ? lane - q * wd : 0;
+    const uint32_t vm = valid_bits(j, g.width), om = bw & ~vm;
+    constexpr int S = kNarrowSteps;
+
+    for (int y = ya; y < yb; y += grp * S) {
+        uint32_t c[S], u[S], d[S];
+        bool live[S];
+        int yy[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            yy[i] = y + i * grp + q;
+            live[i] = lane_used && yy[i] < yb;
+            const int ys = live[i] ? yy[i] : ya;
+            const uint32_t* p = g.in + (int64_t)ys * g.stride + j;
+            c[i] = p[0];
+            u[i] = p[ys > 0 ? -g.stride : 0];
+            d[i] = p[ys + 1 < g.height ? g.stride : 0];
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const uint32_t cc = (c[i] & vm) | om;
+            const uint32_t uu = yy[i] > 0 ? ((u[i] & vm) | om) : bw;
+            const uint32_t dd = yy[i] + 1 < g.height ? ((d[i] & vm) | om) : bw;
+            uint32_t cl = from_lower_lane(cc, bw), cr = from_upper_lane(cc, bw);
+            if (j == 0) cl = bw;
+            if (j == wd - 1) cr = bw;
+            uint32_t ul = bw, ur = bw, dl = bw, dr = bw;
+            if constexpr (MODE != kModePlain) {
+                ul = from_lower_lane(uu, bw); ur = from_upper_lane(uu, bw);
+                dl = from_lower_lane(dd, bw); dr = from_upper_lane(dd, bw);
+                if (j == 0) { ul = bw; dl = bw; }
+                if (j == wd - 1) { ur = bw; dr = bw; }
+            }
+            const uint32_t v = edge_word<MODE>(cc, east_of(uu, ur), uu, west_of(uu, ul),
+                                               west_of(cc, cl), west_of(dd, dl), dd,
+                                               east_of(dd, dr), east_of(cc, cr)) & vm;
+            if (live[i]) g.out[(int64_t)yy[i] * g.stride + j] = invert ? (v ^ vm) : v;
+        }
+    }
+}
+
+// Vector width actually used for a wide image: the largest v <= vmax whose
+// alignment holds (offset and stride in words divisible by v) and whose
+// span 64*v does not leave more than half of the wavefront idle.
+__host__ __device__ inline int pick_vw(int64_t wd, int vmax, int64_t offset_words,
+                                       int64_t stride_words) {
+    int v = vmax;
+    while (v > 1 && ((offset_words % v) != 0 || (stride_words % v) != 0 || wd < 32 * v)) v /= 2;
+    return v;
+}
+
+// Work units of one image (0 for an empty image).
+struct UnitShape {
+    int narrow;       // 1: narrow units, 0: strips
+    int vw;           // strip vector width
+    int64_t chunks;   // strips: word chunks per row
+    int64_t band;     // rows per unit
+    int64_t count;    // units
+};
+
+__host__ __device__ inline UnitShape unit_shape(int64_t height, int64_t width, int64_t wd,
+                                                int64_t offset_words, int64_t stride_words,
+                                                int vmax, int rows) {
+    UnitShape s{0, 1, 0, 1, 0};
+    if (height <= 0 || width <= 0) return s;
+    if (wd <= kNarrowMaxWords) {
+        s.narrow = 1;
+        s.band = (int64_t)(kWave / wd) * rows;
+        s.chunks = 1;
+    } else {
+        s.vw = pick_vw(wd, vmax, offset_words, stride_words);
+        s.chunks = (wd + (int64_t)kWave * s.vw - 1) / ((int64_t)kWave * s.vw);
+        s.band = rows;
+    }
+    s.count = s.chunks * ((height + s.band - 1) / s.band);
+    return s;
+}
+
+}  // namespace edgek

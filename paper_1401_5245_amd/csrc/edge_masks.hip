@@ -1,0 +1,601 @@
+// edge_masks.hip - kernels and C ABI of libedgemask (gfx950).
+//
+// Entry points are declared and documented in include/edge_masks.h. Every
+// entry point validates its arguments on the host before any HIP call,
+// chooses a launch shape, and enqueues asynchronously on the caller's
+// stream. The library allocates no device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <new>
+#include <stdint.h>
+#include <string.h>
+
+#include "edge_device.hpp"
+#include "edge_masks.h"
+
+using namespace edgek;
+
+// ================================================================ kernels ===
+
+// One image, strips of `rows` rows x 64*VW words, one wavefront per strip.
+template <int VW, int MODE>
+__global__ void __launch_bounds__(512) k_strip(Geom g, int64_t chunks, int rows, int64_t nunits,
+                                               uint32_t bw, int invert) {
+    const int wpb = blockDim.x / kWave;
+    const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
+                         wave_uniform(threadIdx.x / kWave);
+    if (unit >= nunits) return;
+    const int64_t strip = unit / chunks;
+    const int64_t chunk = unit - strip * chunks;
+    const int64_t y0 = strip * rows;
+    const int64_t y1 = y0 + rows < g.height ? y0 + rows : g.height;
+    strip_unit<VW, MODE>(g, (int)(chunk * kWave * VW), (int)y0, (int)y1, bw, invert != 0);
+}
+
+// One image with rows of <= 32 words, `band` rows per wavefront.
+template <int MODE>
+__global__ void __launch_bounds__(512) k_narrow(Geom g, int64_t band, int64_t nunits, uint32_t bw,
+                                                int invert) {
+    const int wpb = blockDim.x / kWave;
+    const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
+                         wave_uniform(threadIdx.x / kWave);
+    if (unit >= nunits) return;
+    const int64_t ya = unit * band;
+    const int64_t yb = ya + band < g.height ? ya + band : g.height;
+    narrow_unit<MODE>(g, (int)ya, (int)yb, bw, invert != 0);
+}
+
+// Descriptor check shared by the host validator and the device planner.
+__host__ __device__ static inline bool desc_ok(const edge_image_desc& d, int64_t arena_words,
+                                               int word_bits) {
+    if (d.height < 0 || d.width < 0 || d.offset_words < 0 || d.stride_words < 0) return false;
+    if (d.height == 0 || d.width == 0) return true;
+    const int64_t wd = ((int64_t)d.width + word_bits - 1) / word_bits;
+    if (d.stride_words < wd || wd > arena_words) return false;
+    if ((int64_t)(d.height - 1) > (arena_words - wd) / d.stride_words) return false;
+    const int64_t span = (int64_t)(d.height - 1) * d.stride_words + wd;
+    return d.offset_words <= arena_words - span;
+}
+
+// Workspace layout (int64 words): [0] total units, [1] skipped descriptors,
+// [2..7] reserved, [8 + i] first unit of image i (i = 0..n; [8 + n] = total).
+constexpr int kWsHeader = 8;
+
+// Batch planner: one workgroup of 1024 threads counts the work units of
+// every image and writes their exclusive prefix sum.
+__global__ void __launch_bounds__(1024) k_plan(const edge_image_desc* tab, int n,
+                                               int64_t arena_words, int word_bits, int vmax,
+                                               int rows, int64_t* ws) {
+    __shared__ int64_t wave_sum[16];
+    __shared__ int bad_count;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int nwaves = blockDim.x / kWave;
+    const int per = word_bits / 32;
+    int64_t* start = ws + kWsHeader;
+    if (tid == 0) bad_count = 0;
+    __syncthreads();
+    int64_t carry = 0;
+    for (int base = 0; base < n; base += blockDim.x) {
+        const int i = base + tid;
+        int64_t cnt = 0;
+        if (i < n) {
+            const edge_image_desc d = tab[i];
+            if (desc_ok(d, arena_words, word_bits)) {
+                const int64_t wd = ((int64_t)d.width + word_bits - 1) / word_bits * per;
+                cnt = unit_shape(d.height, d.width, wd, d.offset_words * per,
+                                 d.stride_words * per, vmax, rows).count;
+            } else {
+                atomicAdd(&bad_count, 1);
+            }
+        }
+        int64_t x = cnt;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int64_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == kWave - 1) wave_sum[wave] = x;
+        __syncthreads();
+        int64_t before = 0, total = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            const int64_t s = wave_sum[w];
+            if (w < wave) before += s;
+            total += s;
+        }
+        if (i < n) start[i] = carry + before + x - cnt;
+        carry += total;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        start[n] = carry;
+        ws[0] = carry;
+        ws[1] = bad_count;
+    }
+}
+
+// Persistent batch kernel: wavefront gw of nw processes the contiguous unit
+// range [total*gw/nw, total*(gw+1)/nw) across the images of the table.
+template <int MODE>
+__global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out,
+                                               const edge_image_desc* tab, int n, int word_bits,
+                                               const int64_t* ws, int vmax, int rows, uint32_t bw,
+                                               int invert) {
+    const int wpb = blockDim.x / kWave;
+    const int64_t nw = (int64_t)gridDim.x * wpb;
+    const int64_t gw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
+                       wave_uniform(threadIdx.x / kWave);
+    const int64_t total = ws[0];
+    const int64_t* start = ws + kWsHeader;
+    const int64_t u0 = total * gw / nw;
+    const int64_t u1 = total * (gw + 1) / nw;
+    if (u0 >= u1) return;
+    // Image holding unit u0: the largest i with start[i] <= u0.
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= u0) lo = mid; else hi = mid - 1;
+    }
+    int i = lo;
+    const int per = word_bits / 32;
+    for (int64_t u = u0; u < u1; ++u) {
+        while (start[i + 1] <= u) ++i;
+        const edge_image_desc d = tab[i];
+        const int64_t wd = ((int64_t)d.width + word_bits - 1) / word_bits * per;
+        Geom g;
+        g.in = in + d.offset_words * per;
+        g.out = out + d.offset_words * per;
+        g.stride = d.stride_words * per;
+        g.height = d.height;
+        g.width = d.width;
+        g.wd = (int32_t)wd;
+        const UnitShape s = unit_shape(d.height, d.width, wd, d.offset_words * per,
+                                       d.stride_words * per, vmax, rows);
+        const int64_t local = u - start[i];
+        const int64_t strip = local / s.chunks;
+        const int64_t chunk = local - strip * s.chunks;
+        const int64_t y0 = strip * s.band;
+        const int64_t y1 = y0 + s.band < d.height ? y0 + s.band : d.height;
+        if (s.narrow) {
+            narrow_unit<MODE>(g, (int)y0, (int)y1, bw, invert != 0);
+        } else if (s.vw == 4) {
+            strip_unit<4, MODE>(g, (int)(chunk * kWave * 4), (int)y0, (int)y1, bw, invert != 0);
+        } else if (s.vw == 2) {
+            strip_unit<2, MODE>(g, (int)(chunk * kWave * 2), (int)y0, (int)y1, bw, invert != 0);
+        } else {
+            strip_unit<1, MODE>(g, (int)(chunk * kWave), (int)y0, (int)y1, bw, invert != 0);
+        }
+    }
+}
+
+// Plain 128-bit copy: the bandwidth reference.
+__global__ void __launch_bounds__(256) k_copy(const u32x4* in, u32x4* out, int64_t n16) {
+    constexpr int kPer = 4;
+    const int64_t base = (int64_t)blockIdx.x * blockDim.x * kPer + threadIdx.x;
+    u32x4 v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = base + (int64_t)k * blockDim.x;
+        if (i < n16) v[k] = __builtin_nontemporal_load(in + i);
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = base + (int64_t)k * blockDim.x;
+        if (i < n16) __builtin_nontemporal_store(v[k], out + i);
+    }
+}
+
+// ============================================================== host side ===
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_failed(hipError_t e) {
+    g_last_hip = (int)e;
+    return EDGE_ERR_HIP;
+}
+
+int launch_status() {
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? EDGE_OK : hip_failed(e);
+}
+
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_cu_count[kMaxDevices];
+
+int cu_count(int* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_failed(e);
+    if (dev >= 0 && dev < kMaxDevices) {
+        const int c = g_cu_count[dev].load(std::memory_order_relaxed);
+        if (c > 0) { *out = c; return EDGE_OK; }
+    }
+    int n = 0;
+    e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_failed(e);
+    if (n <= 0) n = 1;
+    if (dev >= 0 && dev < kMaxDevices) g_cu_count[dev].store(n, std::memory_order_relaxed);
+    *out = n;
+    return EDGE_OK;
+}
+
+bool cfg_ok(const edge_launch_cfg& c) {
+    return (c.vec_words == 1 || c.vec_words == 2 || c.vec_words == 4) && c.rows_per_tile >= 1 &&
+           c.rows_per_tile <= 1024 &&
+           (c.waves_per_block == 1 || c.waves_per_block == 2 || c.waves_per_block == 4 ||
+            c.waves_per_block == 8) &&
+           c.blocks_per_cu >= 1 && c.blocks_per_cu <= 32;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int64_t pow2_floor(int64_t v) {
+    int64_t p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+
+int common_checks(int word_bits, int border, int mode, uint32_t flags) {
+    if (word_bits != 32 && word_bits != 64) return EDGE_ERR_INVALID;
+    if (border != EDGE_BORDER_WHITE && border != EDGE_BORDER_BLACK) return EDGE_ERR_INVALID;
+    if (mode != EDGE_MODE_MASKS && mode != EDGE_MODE_FULL) return EDGE_ERR_INVALID;
+    if (flags & ~(uint32_t)(EDGE_FLAG_CLAUSE2_ONLY | EDGE_FLAG_INVERT_OUT)) return EDGE_ERR_INVALID;
+    if ((flags & EDGE_FLAG_CLAUSE2_ONLY) && mode != EDGE_MODE_FULL) return EDGE_ERR_INVALID;
+    return EDGE_OK;
+}
+
+int kernel_mode(int mode, uint32_t flags) {
+    if (mode == EDGE_MODE_MASKS) return kModePlain;
+    return (flags & EDGE_FLAG_CLAUSE2_ONLY) ? kModeClause2 : kModeFull;
+}
+
+uint32_t border_word(int border) { return border == EDGE_BORDER_WHITE ? 0xffffffffu : 0u; }
+
+bool ranges_overlap(uintptr_t a, uint64_t na, uintptr_t b, uint64_t nb) {
+    return a < b + nb && b < a + na;
+}
+
+int alignment_words(uintptr_t p) {
+    if (p % 16 == 0) return 4;
+    if (p % 8 == 0) return 2;
+    return 1;
+}
+
+edge_launch_cfg default_single(int64_t height, int64_t wd32) {
+    edge_launch_cfg c;
+    c.waves_per_block = 4;
+    c.blocks_per_cu = 1;
+    if (wd32 <= kNarrowMaxWords) {
+        const int64_t grp = kWave / wd32;
+        c.vec_words = 1;
+        c.rows_per_tile = (int32_t)pow2_floor(std::max<int64_t>(1, std::min<int64_t>(16, height / (grp * 2048))));
+    } else {
+        c.vec_words = 4;
+        const int v = pick_vw(wd32, 4, 0, 0);
+        const int64_t chunks = ceil_div(wd32, (int64_t)kWave * v);
+        c.rows_per_tile = (int32_t)pow2_floor(std::max<int64_t>(4, std::min<int64_t>(128, chunks * height / 4096)));
+    }
+    return c;
+}
+
+edge_launch_cfg default_batch() {
+    edge_launch_cfg c;
+    c.vec_words = 4;
+    c.rows_per_tile = 8;
+    c.waves_per_block = 4;
+    c.blocks_per_cu = 8;
+    return c;
+}
+
+template <int MODE>
+int launch_single(const Geom& g, int vw, const edge_launch_cfg& c, uint32_t bw, int invert,
+                  hipStream_t stream) {
+    const int threads = c.waves_per_block * kWave;
+    if (g.wd <= kNarrowMaxWords) {
+        const int64_t band = (int64_t)(kWave / g.wd) * c.rows_per_tile;
+        const int64_t nunits = ceil_div(g.height, band);
+        const int64_t blocks = ceil_div(nunits, c.waves_per_block);
+        if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+        hipLaunchKernelGGL(k_narrow<MODE>, dim3((uint32_t)blocks), dim3(threads), 0, stream, g,
+                           band, nunits, bw, invert);
+        return launch_status();
+    }
+    const int64_t chunks = ceil_div(g.wd, (int64_t)kWave * vw);
+    const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
+    const int64_t blocks = ceil_div(nunits, c.waves_per_block);
+    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+    switch (vw) {
+        case 4:
+            hipLaunchKernelGGL((k_strip<4, MODE>), dim3((uint32_t)blocks), dim3(threads), 0,
+                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_strip<2, MODE>), dim3((uint32_t)blocks), dim3(threads), 0,
+                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert);
+            break;
+        default:
+            hipLaunchKernelGGL((k_strip<1, MODE>), dim3((uint32_t)blocks), dim3(threads), 0,
+                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert);
+            break;
+    }
+    return launch_status();
+}
+
+int image_launch(const void* in, void* out, int64_t height, int64_t width, int64_t stride_words,
+                 int word_bits, int border, int mode, uint32_t flags, const edge_launch_cfg* cfg,
+                 void* hip_stream) {
+    int rc = common_checks(word_bits, border, mode, flags);
+    if (rc) return rc;
+    if (height < 0 || width < 0 || stride_words < 0) return EDGE_ERR_INVALID;
+    if (height > 0x7fffffff || width > 0x7fffffff) return EDGE_ERR_INVALID;
+    if (cfg && !cfg_ok(*cfg)) return EDGE_ERR_INVALID;
+    if (height == 0 || width == 0) return EDGE_OK;
+    if (!in || !out) return EDGE_ERR_INVALID;
+    const int64_t wd = ceil_div(width, word_bits);
+    if (stride_words < wd) return EDGE_ERR_INVALID;
+    const int word_bytes = word_bits / 8;
+    const uintptr_t pin = (uintptr_t)in, pout = (uintptr_t)out;
+    if (pin % word_bytes || pout % word_bytes) return EDGE_ERR_ALIGN;
+    if (stride_words > (int64_t)(INT64_MAX / 8) / height) return EDGE_ERR_INVALID;
+    const uint64_t span = (uint64_t)((height - 1) * stride_words + wd) * word_bytes;
+    if (ranges_overlap(pin, span, pout, span)) return EDGE_ERR_ALIAS;
+
+    const int per = word_bits / 32;
+    Geom g;
+    g.in = (const uint32_t*)in;
+    g.out = (uint32_t*)out;
+    g.stride = stride_words * per;
+    g.height = (int32_t)height;
+    g.width = (int32_t)width;
+    g.wd = (int32_t)(wd * per);
+    const edge_launch_cfg c = cfg ? *cfg : default_single(height, g.wd);
+    int vmax = c.vec_words;
+    vmax = std::min(vmax, alignment_words(pin));
+    vmax = std::min(vmax, alignment_words(pout));
+    const int vw = pick_vw(g.wd, vmax, 0, g.stride);
+    const uint32_t bw = border_word(border);
+    const int inv = (flags & EDGE_FLAG_INVERT_OUT) ? 1 : 0;
+    hipStream_t s = (hipStream_t)hip_stream;
+    switch (kernel_mode(mode, flags)) {
+        case kModePlain: return launch_single<kModePlain>(g, vw, c, bw, inv, s);
+        case kModeFull: return launch_single<kModeFull>(g, vw, c, bw, inv, s);
+        default: return launch_single<kModeClause2>(g, vw, c, bw, inv, s);
+    }
+}
+
+struct BatchArgs {
+    const void* in;
+    void* out;
+    int64_t arena_words;
+    const edge_image_desc* table;
+    int32_t n;
+    int word_bits, border, mode;
+    uint32_t flags;
+    edge_launch_cfg cfg;
+    void* ws;
+};
+
+int batch_validate(const void* in_arena, void* out_arena, int64_t arena_words,
+                   const edge_image_desc* table_dev, int32_t n_images, int word_bits, int border,
+                   int mode, uint32_t flags, const edge_launch_cfg* cfg, void* workspace_dev,
+                   int64_t workspace_bytes, BatchArgs* a) {
+    int rc = common_checks(word_bits, border, mode, flags);
+    if (rc) return rc;
+    if (n_images < 0 || arena_words < 0) return EDGE_ERR_INVALID;
+    if (cfg && !cfg_ok(*cfg)) return EDGE_ERR_INVALID;
+    if (!in_arena || !out_arena || !table_dev) return EDGE_ERR_INVALID;
+    const int word_bytes = word_bits / 8;
+    if ((uintptr_t)in_arena % word_bytes || (uintptr_t)out_arena % word_bytes ||
+        (uintptr_t)table_dev % 8)
+        return EDGE_ERR_ALIGN;
+    if (arena_words > INT64_MAX / 8) return EDGE_ERR_INVALID;
+    const uint64_t bytes = (uint64_t)arena_words * word_bytes;
+    if (ranges_overlap((uintptr_t)in_arena, bytes, (uintptr_t)out_arena, bytes))
+        return EDGE_ERR_ALIAS;
+    const int64_t need = edge_batch_workspace_bytes(n_images);
+    if (!workspace_dev || workspace_bytes < need || (uintptr_t)workspace_dev % 256)
+        return EDGE_ERR_WORKSPACE;
+    a->in = in_arena;
+    a->out = out_arena;
+    a->arena_words = arena_words;
+    a->table = table_dev;
+    a->n = n_images;
+    a->word_bits = word_bits;
+    a->border = border;
+    a->mode = mode;
+    a->flags = flags;
+    a->cfg = cfg ? *cfg : default_batch();
+    a->ws = workspace_dev;
+    return EDGE_OK;
+}
+
+template <int MODE>
+int launch_batch_kernel(const BatchArgs& a, int vmax, int blocks, hipStream_t s) {
+    const uint32_t bw = border_word(a.border);
+    const int inv = (a.flags & EDGE_FLAG_INVERT_OUT) ? 1 : 0;
+    hipLaunchKernelGGL(k_batch<MODE>, dim3(blocks), dim3(a.cfg.waves_per_block * kWave), 0, s,
+                       (const uint32_t*)a.in, (uint32_t*)a.out, a.table, a.n, a.word_bits,
+                       (const int64_t*)a.ws, vmax, a.cfg.rows_per_tile, bw, inv);
+    return launch_status();
+}
+
+int batch_enqueue(const BatchArgs& a, hipStream_t s) {
+    int cus = 0;
+    int rc = cu_count(&cus);
+    if (rc) return rc;
+    int vmax = a.cfg.vec_words;
+    vmax = std::min(vmax, alignment_words((uintptr_t)a.in));
+    vmax = std::min(vmax, alignment_words((uintptr_t)a.out));
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, a.table, a.n, a.arena_words,
+                       a.word_bits, vmax, a.cfg.rows_per_tile, (int64_t*)a.ws);
+    rc = launch_status();
+    if (rc) return rc;
+    const int blocks = a.cfg.blocks_per_cu * cus;
+    switch (kernel_mode(a.mode, a.flags)) {
+        case kModePlain: return launch_batch_kernel<kModePlain>(a, vmax, blocks, s);
+        case kModeFull: return launch_batch_kernel<kModeFull>(a, vmax, blocks, s);
+        default: return launch_batch_kernel<kModeClause2>(a, vmax, blocks, s);
+    }
+}
+
+struct EdgeGraph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+}  // namespace
+
+// ================================================================== C ABI ===
+
+extern "C" {
+
+int edge_abi_version(void) { return EDGE_MASKS_ABI_VERSION; }
+
+int edge_last_hip_error(void) { return g_last_hip; }
+
+const char* edge_status_string(int status) {
+    switch (status) {
+        case EDGE_OK: return "ok";
+        case EDGE_ERR_INVALID: return "invalid argument";
+        case EDGE_ERR_ALIGN: return "pointer not aligned to the word size";
+        case EDGE_ERR_ALIAS: return "input and output overlap";
+        case EDGE_ERR_HIP: return "HIP runtime error";
+        case EDGE_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+        case EDGE_ERR_UNSUPPORTED: return "launch configuration not supported";
+        default: return "unknown status";
+    }
+}
+
+int edge_masks(const void* in, void* out, int64_t height, int64_t width, int64_t stride_words,
+               int word_bits, int border, void* hip_stream) {
+    return image_launch(in, out, height, width, stride_words, word_bits, border, EDGE_MODE_MASKS,
+                        0u, nullptr, hip_stream);
+}
+
+int edge_full(const void* in, void* out, int64_t height, int64_t width, int64_t stride_words,
+              int word_bits, int border, uint32_t flags, void* hip_stream) {
+    return image_launch(in, out, height, width, stride_words, word_bits, border, EDGE_MODE_FULL,
+                        flags, nullptr, hip_stream);
+}
+
+int edge_image_launch(const void* in, void* out, int64_t height, int64_t width,
+                      int64_t stride_words, int word_bits, int border, int mode, uint32_t flags,
+                      const edge_launch_cfg* cfg, void* hip_stream) {
+    return image_launch(in, out, height, width, stride_words, word_bits, border, mode, flags, cfg,
+                        hip_stream);
+}
+
+int edge_default_cfg(int64_t height, int64_t width, int word_bits, int mode, int batch,
+                     edge_launch_cfg* cfg_out) {
+    if (!cfg_out || height < 0 || width < 0) return EDGE_ERR_INVALID;
+    if (common_checks(word_bits, EDGE_BORDER_WHITE, mode, 0u)) return EDGE_ERR_INVALID;
+    const int64_t wd32 = ceil_div(width, word_bits) * (word_bits / 32);
+    *cfg_out = batch ? default_batch() : default_single(height, std::max<int64_t>(wd32, 1));
+    return EDGE_OK;
+}
+
+int64_t edge_batch_workspace_bytes(int32_t n_images) {
+    if (n_images < 0) return EDGE_ERR_INVALID;
+    return (int64_t)(kWsHeader + (int64_t)n_images + 1) * 8;
+}
+
+int edge_batch_check(const edge_image_desc* table_host, int32_t n_images, int64_t arena_words,
+                     int word_bits) {
+    if (n_images < 0 || arena_words < 0) return EDGE_ERR_INVALID;
+    if (word_bits != 32 && word_bits != 64) return EDGE_ERR_INVALID;
+    if (n_images > 0 && !table_host) return EDGE_ERR_INVALID;
+    for (int32_t i = 0; i < n_images; ++i)
+        if (!desc_ok(table_host[i], arena_words, word_bits)) return EDGE_ERR_INVALID;
+    return EDGE_OK;
+}
+
+int edge_batch(const void* in_arena, void* out_arena, int64_t arena_words,
+               const edge_image_desc* table_dev, int32_t n_images, int word_bits, int border,
+               int mode, uint32_t flags, const edge_launch_cfg* cfg, void* workspace_dev,
+               int64_t workspace_bytes, void* hip_stream) {
+    BatchArgs a;
+    int rc = batch_validate(in_arena, out_arena, arena_words, table_dev, n_images, word_bits,
+                            border, mode, flags, cfg, workspace_dev, workspace_bytes, &a);
+    if (rc) return rc;
+    if (n_images == 0) return EDGE_OK;
+    return batch_enqueue(a, (hipStream_t)hip_stream);
+}
+
+int edge_batch_graph_create(const void* in_arena, void* out_arena, int64_t arena_words,
+                            const edge_image_desc* table_dev, int32_t n_images, int word_bits,
+                            int border, int mode, uint32_t flags, const edge_launch_cfg* cfg,
+                            void* workspace_dev, int64_t workspace_bytes, void** graph_out) {
+    if (!graph_out) return EDGE_ERR_INVALID;
+    *graph_out = nullptr;
+    BatchArgs a;
+    int rc = batch_validate(in_arena, out_arena, arena_words, table_dev, n_images, word_bits,
+                            border, mode, flags, cfg, workspace_dev, workspace_bytes, &a);
+    if (rc) return rc;
+    hipStream_t s = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_failed(e);
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return hip_failed(e);
+    }
+    rc = batch_enqueue(a, s);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    (void)hipStreamDestroy(s);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_failed(e);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_failed(e);
+    }
+    EdgeGraph* h = new (std::nothrow) EdgeGraph{graph, exec};
+    if (!h) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return EDGE_ERR_INVALID;
+    }
+    *graph_out = h;
+    return EDGE_OK;
+}
+
+int edge_graph_launch(void* graph, void* hip_stream) {
+    if (!graph) return EDGE_ERR_INVALID;
+    const hipError_t e = hipGraphLaunch(((EdgeGraph*)graph)->exec, (hipStream_t)hip_stream);
+    return e == hipSuccess ? EDGE_OK : hip_failed(e);
+}
+
+int edge_graph_destroy(void* graph) {
+    if (!graph) return EDGE_OK;
+    EdgeGraph* h = (EdgeGraph*)graph;
+    hipError_t e1 = hipGraphExecDestroy(h->exec);
+    hipError_t e2 = hipGraphDestroy(h->graph);
+    delete h;
+    if (e1 != hipSuccess) return hip_failed(e1);
+    if (e2 != hipSuccess) return hip_failed(e2);
+    return EDGE_OK;
+}
+
+int edge_copy_bytes(const void* in, void* out, int64_t n_bytes, void* hip_stream) {
+    if (n_bytes < 0 || n_bytes % 16) return EDGE_ERR_INVALID;
+    if (n_bytes == 0) return EDGE_OK;
+    if (!in || !out) return EDGE_ERR_INVALID;
+    if ((uintptr_t)in % 16 || (uintptr_t)out % 16) return EDGE_ERR_ALIGN;
+    if (ranges_overlap((uintptr_t)in, (uint64_t)n_bytes, (uintptr_t)out, (uint64_t)n_bytes))
+        return EDGE_ERR_ALIAS;
+    const int64_t n16 = n_bytes / 16;
+    const int64_t blocks = ceil_div(n16, 256 * 4);
+    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(k_copy, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)hip_stream,
+                       (const u32x4*)in, (u32x4*)out, n16);
+    return launch_status();
+}
+
+}  // extern "C"
