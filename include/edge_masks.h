@@ -98,18 +98,24 @@ typedef struct edge_image_desc {
     int64_t stride_words;
 } edge_image_desc;
 
-/* Launch configuration (all fields > 0; NULL selects the built-in choice).
+/* Launch configuration (NULL selects the built-in choice).
  *   vec_words       32-bit words per lane for wide rows: 1, 2 or 4.
  *   rows_per_tile   rows one wavefront walks down per work unit, 1..1024.
  *   waves_per_block wavefronts per workgroup: 1, 2, 4 or 8.
  *   blocks_per_cu   persistent workgroups per compute unit (batch only),
- *                   1..32; ignored by the single-image calls. */
+ *                   1..32; ignored by the single-image calls.
+ *   cache_policy    EDGE_CACHE_AUTO (by image size), EDGE_CACHE_NORMAL or
+ *                   EDGE_CACHE_STREAM (non-temporal loads and stores);
+ *                   single images only, batches use EDGE_CACHE_NORMAL. */
 typedef struct edge_launch_cfg {
     int32_t vec_words;
     int32_t rows_per_tile;
     int32_t waves_per_block;
     int32_t blocks_per_cu;
+    int32_t cache_policy;
 } edge_launch_cfg;
+
+enum { EDGE_CACHE_AUTO = 0, EDGE_CACHE_NORMAL = 1, EDGE_CACHE_STREAM = 2 };
 
 /* Plain method (Boolean function Edge(p), section 1; stages of sections
  * 3-5). `in`, `out`: device pointers to height rows of stride_words words.

@@ -108,6 +108,27 @@ def default_cfg(height: int, width: int, word_bits: int, mode: str = "masks",
     return c.as_dict()
 
 
+def prepare(inp: torch.Tensor, out: torch.Tensor, height: int, width: int, *,
+            mode: str = "masks", border: str = "white", clause2_only: bool = False,
+            invert: bool = False, cfg=None, stride_words=None, stream=None):
+    """Check the arguments once and return a no-argument callable that
+    enqueues the same launch again (for tight launch loops). The tensors
+    must stay alive while the callable is used."""
+    wb, s = _image_args(inp, out, height, width, stride_words)
+    flags = (EDGE_FLAG_CLAUSE2_ONLY if clause2_only else 0) | (EDGE_FLAG_INVERT_OUT if invert else 0)
+    c = None if cfg is None else (EdgeLaunchCfg.from_dict(cfg) if isinstance(cfg, dict) else cfg)
+    args = (inp.data_ptr(), out.data_ptr(), height, width, s, wb, BORDERS[border], MODES[mode],
+            flags, None if c is None else ctypes.byref(c), stream_handle(stream))
+    fn = _lib.edge_image_launch
+
+    def launch():
+        rc = fn(*args)
+        if rc:
+            check(rc)
+    launch.keep = (inp, out, c)
+    return launch
+
+
 def copy_bytes(src: torch.Tensor, dst: torch.Tensor, n_bytes: int, stream=None) -> None:
     """Plain 128-bit device copy (the bandwidth reference for the kernels)."""
     check(_lib.edge_copy_bytes(src.data_ptr(), dst.data_ptr(), n_bytes, stream_handle(stream)))

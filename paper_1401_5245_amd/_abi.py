@@ -34,9 +34,14 @@ class EdgeImageDesc(ctypes.Structure):
                 ("stride_words", c_i64)]
 
 
+EDGE_CACHE_AUTO = 0
+EDGE_CACHE_NORMAL = 1
+EDGE_CACHE_STREAM = 2
+
+
 class EdgeLaunchCfg(ctypes.Structure):
     _fields_ = [("vec_words", c_i32), ("rows_per_tile", c_i32), ("waves_per_block", c_i32),
-                ("blocks_per_cu", c_i32)]
+                ("blocks_per_cu", c_i32), ("cache_policy", c_i32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -44,7 +49,7 @@ class EdgeLaunchCfg(ctypes.Structure):
     @classmethod
     def from_dict(cls, d: dict) -> "EdgeLaunchCfg":
         return cls(int(d["vec_words"]), int(d["rows_per_tile"]), int(d["waves_per_block"]),
-                   int(d.get("blocks_per_cu", 1)))
+                   int(d.get("blocks_per_cu", 1)), int(d.get("cache_policy", EDGE_CACHE_AUTO)))
 
 
 class EdgeError(RuntimeError):

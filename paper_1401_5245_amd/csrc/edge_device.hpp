@@ -32,11 +32,23 @@
 namespace edgek {
 
 constexpr int kWave = 64;
-constexpr int kPrefetch = 4;   // rows each lane keeps in flight in a strip
 constexpr int kNarrowSteps = 4; // narrow-unit steps loaded ahead of use
 constexpr int kNarrowMaxWords = 32;
 
 enum { kModePlain = 0, kModeFull = 1, kModeClause2 = 2 };
+
+// Compile-time choices of the strip loop: rows kept in flight per lane, and
+// non-temporal (streaming) cache policy for the row loads and stores.
+template <int PREFETCH, bool NT_LOAD, bool NT_STORE>
+struct StripPolicy {
+    static constexpr int prefetch = PREFETCH;
+    static constexpr bool nt_load = NT_LOAD;
+    static constexpr bool nt_store = NT_STORE;
+};
+// Images that fit in the caches keep normal loads and stores (halo rows and
+// the output stay cached for the next consumer); large images stream.
+using CachedStrip = StripPolicy<4, false, false>;
+using StreamingStrip = StripPolicy<4, true, true>;
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -126,29 +138,34 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
     return xcd < rem ? xcd * (q + 1) + idx : rem * (q + 1) + (xcd - rem) * q + idx;
 }
 
-template <int VW>
+template <int VW, bool NT>
 __device__ __forceinline__ void load_words(const uint32_t* p, uint32_t (&w)[VW]) {
     if constexpr (VW == 4) {
-        const u32x4 v = *reinterpret_cast<const u32x4*>(p);
+        const u32x4* vp = reinterpret_cast<const u32x4*>(p);
+        const u32x4 v = NT ? __builtin_nontemporal_load(vp) : *vp;
         w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
     } else if constexpr (VW == 2) {
-        const u32x2 v = *reinterpret_cast<const u32x2*>(p);
+        const u32x2* vp = reinterpret_cast<const u32x2*>(p);
+        const u32x2 v = NT ? __builtin_nontemporal_load(vp) : *vp;
         w[0] = v.x; w[1] = v.y;
     } else {
-        w[0] = *p;
+        w[0] = NT ? __builtin_nontemporal_load(p) : *p;
     }
 }
 
-template <int VW>
+template <int VW, bool NT>
 __device__ __forceinline__ void store_words(uint32_t* p, const uint32_t (&w)[VW]) {
     if constexpr (VW == 4) {
         u32x4 v; v.x = w[0]; v.y = w[1]; v.z = w[2]; v.w = w[3];
-        *reinterpret_cast<u32x4*>(p) = v;
+        if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(p));
+        else *reinterpret_cast<u32x4*>(p) = v;
     } else if constexpr (VW == 2) {
         u32x2 v; v.x = w[0]; v.y = w[1];
-        *reinterpret_cast<u32x2*>(p) = v;
+        if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<u32x2*>(p));
+        else *reinterpret_cast<u32x2*>(p) = v;
     } else {
-        *p = w[0];
+        if constexpr (NT) __builtin_nontemporal_store(w[0], p);
+        else *p = w[0];
     }
 }
 
@@ -161,15 +178,19 @@ __device__ __forceinline__ void store_words(uint32_t* p, const uint32_t (&w)[VW]
 // loaded from a clamped address and stored only when it is inside the row.
 // `bw` is the border word (all ones for a white border, zero for black).
 //
-// Each lane keeps kPrefetch rows in flight in the ring q[]: the slot of the
-// row just consumed is refilled with the row kPrefetch rows further down.
+// EDGES: some word just outside the span lies inside the row, so lanes 0
+// and 63 load it with each row; otherwise both carries are border words.
+//
+// Each lane keeps Pol::prefetch rows in flight in the ring q[]: the slot of
+// the row just consumed is refilled with the row that many rows further down.
 // Loads never branch: rows past y1 re-read row y1 (an L1 hit) and rows
 // outside the image are clamped into it and replaced by the border after
 // the load, so the hardware's in-order load counter waits exactly for the
 // row being consumed.
-template <int VW, int MODE, bool WHOLE>
+template <int VW, int MODE, bool WHOLE, bool EDGES, class Pol>
 __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1, uint32_t bw,
                                            bool invert) {
+    constexpr int P = Pol::prefetch;
     const int lane = threadIdx.x & (kWave - 1);
     const int jl = j0 + lane * VW;
 
@@ -199,12 +220,13 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
         const uint32_t* rp = g.in + (int64_t)yc * g.stride;
         Raw r;
         if constexpr (WHOLE) {
-            load_words<VW>(rp + jl, r.w);
+            load_words<VW, Pol::nt_load>(rp + jl, r.w);
         } else {
 #pragma unroll
             for (int k = 0; k < VW; ++k) r.w[k] = rp[jw[k]];
         }
-        r.e = rp[je_load];
+        if constexpr (EDGES) r.e = rp[je_load];
+        else r.e = bw;
         return r;
     };
 
@@ -217,7 +239,7 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
         Row o;
 #pragma unroll
         for (int k = 0; k < VW; ++k) o.c[k] = inside ? ((r.w[k] & vm[k]) | om[k]) : bw;
-        const uint32_t e = (inside && has_e) ? ((r.e & vme) | ome) : bw;
+        const uint32_t e = (EDGES && inside && has_e) ? ((r.e & vme) | ome) : bw;
         const uint32_t left = from_lower_lane(o.c[VW - 1], e);
         const uint32_t right = from_upper_lane(o.c[0], e);
 #pragma unroll
@@ -238,7 +260,7 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
         }
         uint32_t* op = g.out + (int64_t)y * g.stride;
         if constexpr (WHOLE) {
-            store_words<VW>(op + jl, res);
+            store_words<VW, Pol::nt_store>(op + jl, res);
         } else {
 #pragma unroll
             for (int k = 0; k < VW; ++k)
@@ -248,18 +270,18 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
 
     const Raw ra = load_raw(y0 - 1);
     const Raw rb = load_raw(y0);
-    Raw q[kPrefetch];
+    Raw q[P];
 #pragma unroll
-    for (int u = 0; u < kPrefetch; ++u) q[u] = load_raw(min(y0 + 1 + u, y1));
+    for (int u = 0; u < P; ++u) q[u] = load_raw(min(y0 + 1 + u, y1));
     Row up = shift_row(ra, y0 - 1);
     Row cur = shift_row(rb, y0);
     int r = y0;
-    for (; r + kPrefetch <= y1; r += kPrefetch) {   // whole groups
+    for (; r + P <= y1; r += P) {   // whole groups
 #pragma unroll
-        for (int u = 0; u < kPrefetch; ++u) {
+        for (int u = 0; u < P; ++u) {
             const int y = r + u;
             const Row dn = shift_row(q[u], y + 1);
-            q[u] = load_raw(min(y + 1 + kPrefetch, y1));
+            q[u] = load_raw(min(y + 1 + P, y1));
             emit(y, up, cur, dn);
             up = cur;
             cur = dn;
@@ -270,7 +292,7 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
         }
     }
 #pragma unroll
-    for (int u = 0; u + 1 < kPrefetch; ++u) {        // last partial group
+    for (int u = 0; u + 1 < P; ++u) {        // last partial group
         const int y = r + u;
         if (y < y1) {
             const Row dn = shift_row(q[u], y + 1);
@@ -281,11 +303,18 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
     }
 }
 
-template <int VW, int MODE>
+template <int VW, int MODE, class Pol = CachedStrip>
 __device__ __forceinline__ void strip_unit(const Geom& g, int j0, int y0, int y1, uint32_t bw,
                                            bool invert) {
-    if (j0 + kWave * VW <= g.wd) strip_body<VW, MODE, true>(g, j0, y0, y1, bw, invert);
-    else strip_body<VW, MODE, false>(g, j0, y0, y1, bw, invert);
+    const bool whole = j0 + kWave * VW <= g.wd;
+    const bool edges = j0 > 0 || j0 + kWave * VW < g.wd;
+    if (whole) {
+        if (edges) strip_body<VW, MODE, true, true, Pol>(g, j0, y0, y1, bw, invert);
+        else strip_body<VW, MODE, true, false, Pol>(g, j0, y0, y1, bw, invert);
+    } else {
+        if (edges) strip_body<VW, MODE, false, true, Pol>(g, j0, y0, y1, bw, invert);
+        else strip_body<VW, MODE, false, false, Pol>(g, j0, y0, y1, bw, invert);
+    }
 }
 
 // --------------------------------------------------------- narrow units ----

@@ -20,7 +20,7 @@ using namespace edgek;
 // ================================================================ kernels ===
 
 // One image, strips of `rows` rows x 64*VW words, one wavefront per strip.
-template <int VW, int MODE>
+template <int VW, int MODE, class Pol>
 __global__ void __launch_bounds__(512) k_strip(Geom g, int64_t chunks, int rows, int64_t nunits,
                                                uint32_t bw, int invert) {
     const int wpb = blockDim.x / kWave;
@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(512) k_strip(Geom g, int64_t chunks, int rows,
     const int64_t chunk = unit - strip * chunks;
     const int64_t y0 = strip * rows;
     const int64_t y1 = y0 + rows < g.height ? y0 + rows : g.height;
-    strip_unit<VW, MODE>(g, (int)(chunk * kWave * VW), (int)y0, (int)y1, bw, invert != 0);
+    strip_unit<VW, MODE, Pol>(g, (int)(chunk * kWave * VW), (int)y0, (int)y1, bw, invert != 0);
 }
 
 // One image with rows of <= 32 words, `band` rows per wavefront.
@@ -226,7 +226,8 @@ bool cfg_ok(const edge_launch_cfg& c) {
            c.rows_per_tile <= 1024 &&
            (c.waves_per_block == 1 || c.waves_per_block == 2 || c.waves_per_block == 4 ||
             c.waves_per_block == 8) &&
-           c.blocks_per_cu >= 1 && c.blocks_per_cu <= 32;
+           c.blocks_per_cu >= 1 && c.blocks_per_cu <= 32 && c.cache_policy >= EDGE_CACHE_AUTO &&
+           c.cache_policy <= EDGE_CACHE_STREAM;
 }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -263,22 +264,31 @@ int alignment_words(uintptr_t p) {
     return 1;
 }
 
+// Built-in single-image shape. Rows of <= 32 words: narrow units of up to
+// 16 steps. Wider rows: about 2048 strips (8 per compute unit), each at
+// least 2 and at most 256 rows tall.
 edge_launch_cfg default_single(int64_t height, int64_t wd32) {
     edge_launch_cfg c;
-    c.waves_per_block = 4;
     c.blocks_per_cu = 1;
+    c.cache_policy = EDGE_CACHE_AUTO;
     if (wd32 <= kNarrowMaxWords) {
         const int64_t grp = kWave / wd32;
         c.vec_words = 1;
+        c.waves_per_block = 4;
         c.rows_per_tile = (int32_t)pow2_floor(std::max<int64_t>(1, std::min<int64_t>(16, height / (grp * 2048))));
     } else {
         c.vec_words = 4;
         const int v = pick_vw(wd32, 4, 0, 0);
         const int64_t chunks = ceil_div(wd32, (int64_t)kWave * v);
-        c.rows_per_tile = (int32_t)pow2_floor(std::max<int64_t>(4, std::min<int64_t>(128, chunks * height / 4096)));
+        c.rows_per_tile = (int32_t)pow2_floor(std::max<int64_t>(2, std::min<int64_t>(256, chunks * height / 2048)));
+        c.waves_per_block = c.rows_per_tile >= 16 ? 8 : 4;
     }
     return c;
 }
+
+// Streaming (non-temporal) loads and stores pay off once an image's
+// traffic no longer fits comfortably in the last-level cache.
+constexpr int64_t kStreamBytes = 48ll << 20;
 
 edge_launch_cfg default_batch() {
     edge_launch_cfg c;
@@ -286,7 +296,29 @@ edge_launch_cfg default_batch() {
     c.rows_per_tile = 8;
     c.waves_per_block = 4;
     c.blocks_per_cu = 8;
+    c.cache_policy = EDGE_CACHE_NORMAL;
     return c;
+}
+
+template <int MODE, class Pol>
+int launch_strip(const Geom& g, int vw, int64_t chunks, const edge_launch_cfg& c, int64_t nunits,
+                 int64_t blocks, uint32_t bw, int invert, hipStream_t stream) {
+    const int threads = c.waves_per_block * kWave;
+    switch (vw) {
+        case 4:
+            hipLaunchKernelGGL((k_strip<4, MODE, Pol>), dim3((uint32_t)blocks), dim3(threads), 0,
+                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_strip<2, MODE, Pol>), dim3((uint32_t)blocks), dim3(threads), 0,
+                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert);
+            break;
+        default:
+            hipLaunchKernelGGL((k_strip<1, MODE, Pol>), dim3((uint32_t)blocks), dim3(threads), 0,
+                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert);
+            break;
+    }
+    return launch_status();
 }
 
 template <int MODE>
@@ -306,21 +338,13 @@ int launch_single(const Geom& g, int vw, const edge_launch_cfg& c, uint32_t bw, 
     const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
     const int64_t blocks = ceil_div(nunits, c.waves_per_block);
     if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
-    switch (vw) {
-        case 4:
-            hipLaunchKernelGGL((k_strip<4, MODE>), dim3((uint32_t)blocks), dim3(threads), 0,
-                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert);
-            break;
-        case 2:
-            hipLaunchKernelGGL((k_strip<2, MODE>), dim3((uint32_t)blocks), dim3(threads), 0,
-                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert);
-            break;
-        default:
-            hipLaunchKernelGGL((k_strip<1, MODE>), dim3((uint32_t)blocks), dim3(threads), 0,
-                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert);
-            break;
-    }
-    return launch_status();
+    bool stream_mode = c.cache_policy == EDGE_CACHE_STREAM;
+    if (c.cache_policy == EDGE_CACHE_AUTO)
+        stream_mode = 2 * (int64_t)g.height * g.wd * 4 >= kStreamBytes;
+    if (stream_mode)
+        return launch_strip<MODE, StreamingStrip>(g, vw, chunks, c, nunits, blocks, bw, invert,
+                                                  stream);
+    return launch_strip<MODE, CachedStrip>(g, vw, chunks, c, nunits, blocks, bw, invert, stream);
 }
 
 int image_launch(const void* in, void* out, int64_t height, int64_t width, int64_t stride_words,

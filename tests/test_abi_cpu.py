@@ -73,8 +73,9 @@ def test_mode_flag_and_cfg_validation():
     assert launch(flags=4) == INVALID
     assert launch(mode=0, flags=_abi.EDGE_FLAG_CLAUSE2_ONLY) == INVALID
     assert lib.edge_full(A, B, 4, 100, 4, 32, 0, 8, None) == INVALID
-    for bad in ((3, 4, 4, 1), (4, 0, 4, 1), (4, 4, 3, 1), (4, 4, 4, 0), (4, 2000, 4, 1),
-                (4, 4, 16, 1), (4, 4, 4, 33)):
+    for bad in ((3, 4, 4, 1, 0), (4, 0, 4, 1, 0), (4, 4, 3, 1, 0), (4, 4, 4, 0, 0),
+                (4, 2000, 4, 1, 0), (4, 4, 16, 1, 0), (4, 4, 4, 33, 0), (4, 4, 4, 1, 3),
+                (4, 4, 4, 1, -1)):
         cfg = _abi.EdgeLaunchCfg(*bad)
         assert launch(cfg=ctypes.byref(cfg)) == INVALID, bad
     # adjacent, non-overlapping buffers are fine up to the launch; exactly

@@ -58,11 +58,7 @@ def test_strides_pads_and_alignment(word_bits):
     img = rand_img(50, 3000, 0.5, seed=9)
     want = expect(img)
     for stride_extra in (0, 1, 2, 3, 7):
-        for offset in (0, 1, 2, 3):
-            if word_bits == 64 and offset:
-                offset_w = offset  # 8-byte aligned, not always 16
-            else:
-                offset_w = offset
+        for offset_w in (0, 1, 2, 3):     # misaligns the pointers for 128-bit access
             for pad in ("zero", "ones", "random"):
                 _, got = run_single(img, word_bits, stride_extra=stride_extra, pad=pad,
                                     offset_words=offset_w)
@@ -72,8 +68,10 @@ def test_strides_pads_and_alignment(word_bits):
 @pytest.mark.parametrize("vec", [1, 2, 4])
 @pytest.mark.parametrize("rows", [1, 3, 4, 5, 8, 17, 64])
 @pytest.mark.parametrize("waves", [1, 2, 4, 8])
-def test_launch_configs(vec, rows, waves):
-    cfg = dict(vec_words=vec, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=1)
+@pytest.mark.parametrize("cache", [1, 2])
+def test_launch_configs(vec, rows, waves, cache):
+    cfg = dict(vec_words=vec, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=1,
+               cache_policy=cache)
     for (H, W, wb) in ((70, 4100, 64), (33, 1000, 32), (9, 300, 32), (100, 700, 64)):
         img = rand_img(H, W, 0.5, seed=H + W + vec)
         for mode, c2 in (("masks", False), ("full", True)):
