@@ -42,6 +42,8 @@ def parse():
                    help="time only the headline workload (no other configs, no CPU baseline)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--serve-only", action="store_true",
+                   help="run only the serving sweep (prints its JSON)")
     return p.parse_args()
 
 
@@ -346,6 +348,52 @@ def batched_crops(torch, em, tm, steps):
             "bit_exact_first_256": exact}
 
 
+def serving(torch, em, p99_bound_ms=20.0, budget=4 << 30):
+    """Poisson request stream over a 64-image pool (sides log-uniform in
+    [64, 4096], half glyph pages, half Bernoulli(0.3)); sweep the offered
+    rate for the batched server and the per-request-launch server; report
+    the highest rate each sustains with p99 latency within the bound."""
+    from synth import images, pack_rows, row_words
+    from paper_1401_5245_amd.serve import Pool, Server, poisson_arrivals
+    log("generating the serving pool (seed 5)")
+    pool_imgs = images.serving_pool(64, seed=5)
+    packed = []
+    for im, _ in pool_imgs:
+        wd = row_words(im.shape[1], 64)
+        packed.append((pack_rows(im, 64, wd + wd % 2), im.shape[1]))
+    pool = Pool.from_images(packed, 64)
+    mean_px = float(pool.pixels.mean())
+    srv = Server(pool, budget, max_inflight=3)
+    rng = np.random.default_rng(55)
+    out = {"workload": "serving: Poisson arrivals, 64-image pool, sides log-uniform [64,4096], "
+                       "half glyph / half Bernoulli(0.3), uint64; HBM budget %d GiB, 3 batches "
+                       "in flight" % (budget >> 30),
+           "mean_mpx_per_request": round(mean_px / 1e6, 3), "p99_bound_ms": p99_bound_ms}
+    for name, per_req, rates in (("batched", False, (5e3, 1e4, 2e4, 4e4, 8e4, 1.6e5)),
+                                 ("per_request", True, (2e3, 5e3, 1e4, 2e4, 4e4))):
+        runs, best = [], None
+        for rate in rates:
+            n = int(min(max(200, rate * 0.4), 8000))
+            arr = poisson_arrivals(n, rate, seed=int(rate))
+            idx = rng.integers(0, len(pool_imgs), size=n)
+            srv.run(arr[:50], idx[:50], per_request=per_req)          # warm-up
+            st = srv.run(arr, idx, per_request=per_req).summary()
+            st["offered_rps"] = rate
+            runs.append(st)
+            log(f"serve {name} rate={rate:.0f}/s p50={st['p50_ms']} p99={st['p99_ms']} "
+                f"gpx_s={st['gpx_s']} batches={st['batches']}")
+            if st["p99_ms"] <= p99_bound_ms:
+                best = st
+        out[name] = {"runs": runs,
+                     "max_sustained": None if best is None else {
+                         "offered_rps": best["offered_rps"], "gpx_s": best["gpx_s"],
+                         "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"]}}
+    b, p = out["batched"]["max_sustained"], out["per_request"]["max_sustained"]
+    if b and p:
+        out["speedup_at_p99_bound"] = round(b["gpx_s"] / p["gpx_s"], 2)
+    return out
+
+
 def cpu_baseline(img, seconds):
     import oracle
     t0 = time.perf_counter()
@@ -374,6 +422,9 @@ def main():
         log("no GPU visible")
         sys.exit(1)
     tm = Timer(torch)
+    if args.serve_only:
+        print(json.dumps(serving(torch, em)), flush=True)
+        return
     img, ms, eager_ms, timed, exact = headline(torch, em, tm, args.steps, args.warmup)
     H = W = 8192
     gpx = H * W / (ms * 1e-3) / 1e9
@@ -409,6 +460,8 @@ def main():
         extra["full_16384"] = full_16384(torch, em, tm, 50)
         log("config: batched crops")
         extra["batched_4096"] = batched_crops(torch, em, tm, args.steps)
+        log("config: serving")
+        extra["serving"] = serving(torch, em)
         res["extra"] = extra
     print(json.dumps(res), flush=True)
 

@@ -150,8 +150,8 @@ class Batch:
     """
 
     def __init__(self, images, word_bits: int, device="cuda", *, border="white",
-                 mode="masks", clause2_only=False, invert=False, cfg=None):
-        arena, table = pack_arena(images, word_bits)
+                 mode="masks", clause2_only=False, invert=False, cfg=None, align_words=None):
+        arena, table = pack_arena(images, word_bits, align_words)
         check_table(table, arena.size, word_bits)
         self.word_bits = word_bits
         self.table = table

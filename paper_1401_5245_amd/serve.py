@@ -1,0 +1,355 @@
+"""Continuous-batching server for binary edge maps on one GPU.
+
+Requests (packed images already in pinned host memory) arrive on a
+schedule. The server admits them in arrival order while the device ring
+arena (the HBM budget) has room, copies each admitted group to the device
+with as few copies as the layout allows, and whenever a launch slot is free
+sends every admitted request not yet launched into one persistent batched
+launch (``edge_batch``). Up to ``max_inflight`` batches are on the device at
+once, each moving through three streams: copy-in, compute, copy-out; a
+batch's arena space is released when its results are back in host memory,
+and the next arrivals are admitted into it. Latency is measured from a
+request's scheduled arrival to the moment its result is in host memory.
+
+``per_request=True`` runs the same loop with one plain ``edge_masks``
+launch (and its own copy-out) per request: the per-request-launch server
+that batching is compared against.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import batch as _batch
+from ._abi import EdgeError, EDGE_ERR_INVALID
+
+
+class RingArena:
+    """FIFO ring allocator over [0, capacity) words.
+
+    Blocks are taken at the head and released oldest first; a block never
+    straddles the end of the ring (the tail gap is skipped). Offsets are
+    rounded up to `align` words.
+    """
+
+    def __init__(self, capacity: int, align: int = 2):
+        self.capacity = int(capacity)
+        self.align = int(align)
+        self.blocks = collections.deque()   # (offset, size)
+        self.head = 0
+        self.used = 0
+
+    def _round(self, n):
+        return -(-int(n) // self.align) * self.align
+
+    def alloc(self, n: int):
+        """Offset of a new block of n words, or None when it does not fit now."""
+        n = self._round(n)
+        if n <= 0 or n > self.capacity:
+            raise ValueError(f"block of {n} words cannot fit a ring of {self.capacity}")
+        if not self.blocks:
+            off = 0
+        else:
+            first = self.blocks[0][0]
+            if self.head > first:                 # live region [first, head)
+                if self.head + n <= self.capacity:
+                    off = self.head
+                elif n <= first:
+                    off = 0
+                else:
+                    return None
+            else:                                 # wrapped: free [head, first)
+                if self.head + n <= first:
+                    off = self.head
+                else:
+                    return None
+        self.blocks.append((off, n))
+        self.head = off + n
+        self.used += n
+        return off
+
+    def free_oldest(self):
+        off, n = self.blocks.popleft()
+        self.used -= n
+        if not self.blocks:
+            self.head = 0
+        return off, n
+
+
+@dataclass
+class Request:
+    rid: int
+    pool_index: int
+    arrival: float                   # scheduled arrival, seconds from start
+    admitted: float = -1.0
+    launched: float = -1.0
+    kernel_done: float = -1.0
+    done: float = -1.0
+    offset: int = -1                 # device arena offset (words)
+    rejected: bool = False
+    ev_in: object = None             # event after the copy that brought it in
+
+
+@dataclass
+class Pool:
+    """Packed request images in one pinned host buffer.
+
+    host_in: pinned words of every pool image back to back (16-byte aligned
+    offsets); host_out: pinned buffer of the same layout for results.
+    """
+    host_in: torch.Tensor
+    host_out: torch.Tensor
+    table: np.ndarray                # DESC_DTYPE, offsets into host_in
+    word_bits: int
+    pixels: np.ndarray               # H*W per image
+
+    @classmethod
+    def from_images(cls, packed, word_bits: int):
+        arena, table = _batch.pack_arena(packed, word_bits)
+        view = np.int64 if word_bits == 64 else np.int32
+        host_in = torch.from_numpy(arena.view(view)).pin_memory()
+        host_out = torch.zeros_like(host_in).pin_memory()
+        pixels = table["height"].astype(np.int64) * table["width"].astype(np.int64)
+        return cls(host_in, host_out, table, word_bits, pixels)
+
+    def words(self, i: int) -> int:
+        d = self.table[i]
+        return int(d["height"]) * int(d["stride_words"])
+
+
+@dataclass
+class _Batch:
+    reqs: list
+    slot: int
+    ev_kernel: object
+    ev_done: object
+
+
+@dataclass
+class Stats:
+    latencies_ms: np.ndarray
+    latencies_no_d2h_ms: np.ndarray
+    queue_ms: np.ndarray
+    pixels: int
+    duration_s: float
+    n_batches: int
+    rejected: int
+    extra: dict = field(default_factory=dict)
+
+    def summary(self) -> dict:
+        lat = self.latencies_ms
+        q = (lambda a, p: float(np.percentile(a, p)) if a.size else float("nan"))
+        return {"requests": int(lat.size), "rejected": self.rejected, "batches": self.n_batches,
+                "p50_ms": round(q(lat, 50), 3), "p99_ms": round(q(lat, 99), 3),
+                "max_ms": round(float(lat.max()) if lat.size else float("nan"), 3),
+                "p50_ms_no_d2h": round(q(self.latencies_no_d2h_ms, 50), 3),
+                "p99_ms_no_d2h": round(q(self.latencies_no_d2h_ms, 99), 3),
+                "p50_queue_ms": round(q(self.queue_ms, 50), 3),
+                "gpx_s": round(self.pixels / self.duration_s / 1e9, 3) if self.duration_s else 0.0,
+                "duration_s": round(self.duration_s, 4), **self.extra}
+
+
+def _runs(src_offs, dst_offs, sizes):
+    """Merge (src, dst, n) copies into runs contiguous on both sides."""
+    runs = []
+    for s, d, n in zip(src_offs, dst_offs, sizes):
+        if runs and runs[-1][0] + runs[-1][2] == s and runs[-1][1] + runs[-1][2] == d:
+            runs[-1][2] += n
+        else:
+            runs.append([s, d, n])
+    return runs
+
+
+class Server:
+    """One-GPU continuous-batching server over a pinned request pool."""
+
+    def __init__(self, pool: Pool, budget_bytes: int, *, max_inflight: int = 3,
+                 max_batch: int = 4096, border: str = "white", mode: str = "masks",
+                 cfg=None, device="cuda"):
+        self.pool = pool
+        wb = pool.word_bits
+        self.word_bytes = wb // 8
+        cap = int(budget_bytes) // 2 // self.word_bytes      # each of in and out arenas
+        align = 128 // wb
+        cap -= cap % align
+        self.ring = RingArena(cap, align)
+        dt = torch.int64 if wb == 64 else torch.int32
+        self.dev_in = torch.zeros(cap, dtype=dt, device=device)
+        self.dev_out = torch.zeros(cap, dtype=dt, device=device)
+        self.max_inflight = max_inflight
+        self.max_batch = max_batch
+        self.kw = dict(border=border, mode=mode, cfg=cfg)
+        self.s_in = torch.cuda.Stream(device)
+        self.s_k = torch.cuda.Stream(device)
+        self.s_out = torch.cuda.Stream(device)
+        nb = _batch.batch_workspace_bytes(max_batch)
+        self.slots = []
+        for _ in range(max_inflight):
+            self.slots.append({
+                "table_host": torch.zeros(max_batch * 3, dtype=torch.int64).pin_memory(),
+                "table_dev": torch.zeros(max_batch * 3, dtype=torch.int64, device=device),
+                "ws": torch.zeros(-(-nb // 8), dtype=torch.int64, device=device),
+                "busy": False})
+        self._tab = np.zeros(max_batch, dtype=_batch.DESC_DTYPE)
+
+    # ---------------------------------------------------------------- loop --
+
+    def run(self, arrivals: np.ndarray, pool_index: np.ndarray, *, per_request: bool = False,
+            record_outputs: bool = False) -> Stats:
+        """Serve requests r = 0..n-1 arriving at `arrivals[r]` seconds with
+        image pool_index[r]. Blocks until every request is answered."""
+        import paper_1401_5245_amd as em
+        pool = self.pool
+        n = len(arrivals)
+        reqs = [Request(i, int(pool_index[i]), float(arrivals[i])) for i in range(n)]
+        words = np.array([pool.words(int(p)) for p in pool_index], dtype=np.int64)
+        waiting = collections.deque(range(n))
+        admitted = collections.deque()
+        inflight = collections.deque()
+        out_of = [None] * n if record_outputs else None
+        nbatches = 0
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0  # noqa: E731
+        dev_in, dev_out, host_in, host_out = self.dev_in, self.dev_out, pool.host_in, pool.host_out
+        table = pool.table
+        rejected = 0
+
+        while waiting or admitted or inflight:
+            progressed = False
+            # 1. completions, oldest first (the ring frees in order)
+            while inflight and inflight[0].ev_done.query():
+                b = inflight.popleft()
+                t = now()
+                for r in b.reqs:
+                    r.done = t
+                    self.ring.free_oldest()
+                    if record_outputs:
+                        o = int(table[r.pool_index]["offset_words"])
+                        out_of[r.rid] = host_out[o:o + words[r.rid]].clone()
+                self.slots[b.slot]["busy"] = False
+                progressed = True
+            for b in inflight:
+                if b.reqs[0].kernel_done < 0 and b.ev_kernel.query():
+                    t = now()
+                    for r in b.reqs:
+                        r.kernel_done = t
+            # 2. admission in arrival order while the ring has room
+            t = now()
+            newly = []
+            while waiting and reqs[waiting[0]].arrival <= t:
+                r = reqs[waiting[0]]
+                if self.ring._round(words[r.rid]) > self.ring.capacity:
+                    r.rejected = True          # larger than the whole budget
+                    rejected += 1
+                    waiting.popleft()
+                    continue
+                if words[r.rid] == 0:          # empty image: nothing to compute
+                    r.admitted = r.launched = r.kernel_done = r.done = t
+                    waiting.popleft()
+                    continue
+                off = self.ring.alloc(words[r.rid])
+                if off is None:
+                    break                      # wait for space to free up
+                r.offset = off
+                r.admitted = t
+                waiting.popleft()
+                newly.append(r)
+            if newly:
+                runs = _runs([int(table[r.pool_index]["offset_words"]) for r in newly],
+                             [r.offset for r in newly], [int(words[r.rid]) for r in newly])
+                with torch.cuda.stream(self.s_in):
+                    for s, d, m in runs:
+                        dev_in[d:d + m].copy_(host_in[s:s + m], non_blocking=True)
+                    ev = torch.cuda.Event()
+                    ev.record(self.s_in)
+                for r in newly:
+                    r.ev_in = ev
+                admitted.extend(newly)
+                progressed = True
+            # 3. launch: every admitted request not yet launched (continuous batching)
+            if admitted:
+                slot = next((i for i, s in enumerate(self.slots) if not s["busy"]), None)
+                if slot is not None:
+                    take = 1 if per_request else min(len(admitted), self.max_batch)
+                    group = [admitted.popleft() for _ in range(take)]
+                    seen = set()
+                    for r in group:                 # the copies that brought the group in
+                        if id(r.ev_in) not in seen:
+                            seen.add(id(r.ev_in))
+                            self.s_k.wait_event(r.ev_in)
+                    S = self.slots[slot]
+                    t = now()
+                    with torch.cuda.stream(self.s_k):
+                        if per_request:
+                            r = group[0]
+                            d = table[r.pool_index]
+                            H, W, St = int(d["height"]), int(d["width"]), int(d["stride_words"])
+                            m = int(words[r.rid])
+                            em.edge_image(dev_in[r.offset:r.offset + m],
+                                          dev_out[r.offset:r.offset + m], H, W,
+                                          stride_words=St, border=self.kw["border"],
+                                          mode=self.kw["mode"], stream=self.s_k)
+                        else:
+                            k = len(group)
+                            tab = self._tab[:k]
+                            pidx = np.fromiter((r.pool_index for r in group), np.int64, k)
+                            tab["offset_words"] = np.fromiter((r.offset for r in group),
+                                                              np.int64, k)
+                            tab["height"] = table["height"][pidx]
+                            tab["width"] = table["width"][pidx]
+                            tab["stride_words"] = table["stride_words"][pidx]
+                            th = S["table_host"]
+                            th[:k * 3].numpy()[:] = tab.view(np.int64)
+                            S["table_dev"][:k * 3].copy_(th[:k * 3], non_blocking=True)
+                            _batch.edge_batch(dev_in, dev_out, S["table_dev"], k, S["ws"],
+                                              stream=self.s_k, **self.kw)
+                        ev_k = torch.cuda.Event()
+                        ev_k.record(self.s_k)
+                    self.s_out.wait_event(ev_k)
+                    runs = _runs([r.offset for r in group],
+                                 [int(table[r.pool_index]["offset_words"]) for r in group],
+                                 [int(words[r.rid]) for r in group])
+                    with torch.cuda.stream(self.s_out):
+                        for s, d, m in runs:
+                            host_out[d:d + m].copy_(dev_out[s:s + m], non_blocking=True)
+                        ev_d = torch.cuda.Event()
+                        ev_d.record(self.s_out)
+                    for r in group:
+                        r.launched = t
+                    S["busy"] = True
+                    inflight.append(_Batch(group, slot, ev_k, ev_d))
+                    nbatches += 1
+                    progressed = True
+            if not progressed:
+                if not admitted and not inflight and waiting:
+                    gap = reqs[waiting[0]].arrival - now()
+                    if gap > 2e-4:
+                        time.sleep(gap - 1e-4)
+                else:
+                    time.sleep(0)
+        served = [r for r in reqs if not r.rejected and words[r.rid] > 0]
+        lat = np.array([(r.done - r.arrival) * 1e3 for r in served])
+        lat_k = np.array([((r.kernel_done if r.kernel_done >= 0 else r.done) - r.arrival) * 1e3
+                          for r in served])
+        queue = np.array([(r.launched - r.arrival) * 1e3 for r in served])
+        pixels = int(sum(int(pool.pixels[r.pool_index]) for r in served))
+        t_first = min((r.arrival for r in served), default=0.0)
+        t_last = max((r.done for r in served), default=0.0)
+        st = Stats(lat, lat_k, queue, pixels, t_last - t_first, nbatches, rejected)
+        if record_outputs:
+            st.extra["outputs"] = out_of
+        return st
+
+
+def poisson_arrivals(n: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of `rate` requests/s."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+__all__ = ["RingArena", "Pool", "Server", "Stats", "poisson_arrivals", "EdgeError",
+           "EDGE_ERR_INVALID"]

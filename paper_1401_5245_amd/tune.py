@@ -1,0 +1,243 @@
+"""Autotuner for launch configurations (words per lane, rows per tile,
+wavefronts per workgroup, persistent workgroups per CU, cache policy).
+
+Each candidate is timed on the device from a captured graph of repeated
+launches (so host launch overhead does not decide), and is admitted only
+when its output equals, bit for bit, the output of the library's built-in
+configuration on the same input. Winners are cached in a JSON file keyed by
+GPU architecture, word size, mode and a size class.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+import threading
+
+import torch
+
+from . import _abi
+
+_lock = threading.Lock()
+
+DEFAULT_CACHE = os.environ.get(
+    "EDGEMASK_TUNE_CACHE",
+    os.path.join(os.path.expanduser("~"), ".cache", "edgemask", "tune.json"))
+SHIPPED_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json")
+
+
+def arch() -> str:
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def size_class(height: int, width: int, word_bits: int) -> str:
+    """Coarse shape bucket: log2 of the 32-bit words per row and of the rows."""
+    wd32 = max(1, -(-width // word_bits) * (word_bits // 32))
+    return f"w{int(math.log2(wd32))}_h{int(math.log2(max(1, height)))}"
+
+
+def image_key(height, width, word_bits, mode="masks") -> str:
+    return f"{arch()}|image|B{word_bits}|{mode}|{size_class(height, width, word_bits)}"
+
+
+def batch_key(n_images, total_words, word_bits, mode="masks") -> str:
+    return (f"{arch()}|batch|B{word_bits}|{mode}|n{int(math.log2(max(1, n_images)))}"
+            f"_s{int(math.log2(max(1, total_words)))}")
+
+
+class TuneCache:
+    """JSON table of tuned configurations (shipped table + user cache)."""
+
+    def __init__(self, path: str = DEFAULT_CACHE):
+        self.path = path
+        self.table = {}
+        for p in (SHIPPED_TABLE, path):
+            if os.path.exists(p):
+                with open(p) as f:
+                    self.table.update(json.load(f))
+
+    def get(self, key):
+        return self.table.get(key, {}).get("cfg")
+
+    def put(self, key, cfg, us, candidates):
+        self.table[key] = {"cfg": cfg, "us": round(us, 3), "candidates": candidates}
+
+    def save(self, path: str | None = None):
+        path = path or self.path
+        with _lock:
+            os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+            tmp = path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.table, f, indent=1, sort_keys=True)
+            os.replace(tmp, path)
+
+
+def _graph_time_us(fn, launches: int, reps: int) -> float:
+    """Device time per call of fn, from a graph of `launches` calls."""
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        for _ in range(launches):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        g.replay()
+    b.record()
+    b.synchronize()
+    del g
+    return a.elapsed_time(b) * 1e3 / (reps * launches)
+
+
+def image_candidates(height: int, width: int, word_bits: int):
+    wd32 = -(-width // word_bits) * (word_bits // 32)
+    if wd32 <= 32:
+        for rows, waves in itertools.product((1, 2, 4, 8, 16), (1, 2, 4, 8)):
+            yield dict(vec_words=1, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=1,
+                       cache_policy=1)
+        return
+    for vec, rows, waves, cache in itertools.product((2, 4), (2, 4, 8, 16, 32, 64, 128, 256),
+                                                     (2, 4, 8), (1, 2)):
+        if rows > max(2, height):
+            continue
+        yield dict(vec_words=vec, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=1,
+                   cache_policy=cache)
+
+
+def tune_image(inp, out, height, width, *, mode="masks", border="white", candidates=None,
+               cache: TuneCache | None = None, launches=20, reps=3, verbose=False):
+    """Time every candidate on (inp, out); keep the fastest whose output
+    equals the built-in configuration's. Returns (cfg, microseconds)."""
+    import paper_1401_5245_amd as em
+    em.edge_image(inp, out, height, width, mode=mode, border=border)
+    torch.cuda.synchronize()
+    ref = out.clone()
+    best, best_us, tried = None, float("inf"), 0
+    cands = list(candidates) if candidates is not None else list(
+        image_candidates(height, width, em.word_bits_of(inp)))
+    for c in cands:
+        out.zero_()
+        em.edge_image(inp, out, height, width, mode=mode, border=border, cfg=c)
+        torch.cuda.synchronize()
+        if not torch.equal(out, ref):
+            if verbose:
+                print("rejected (output differs):", c)
+            continue
+        us = _graph_time_us(lambda: em.edge_image(inp, out, height, width, mode=mode,
+                                                  border=border, cfg=c), launches, reps)
+        tried += 1
+        if verbose:
+            print(f"{us:9.2f} us  {c}")
+        if us < best_us:
+            best, best_us = c, us
+    if best is None:
+        raise RuntimeError("no candidate configuration matched the built-in output")
+    if cache is not None:
+        cache.put(image_key(height, width, em.word_bits_of(inp), mode), best, best_us, tried)
+    return best, best_us
+
+
+def batch_candidates():
+    for vec, rows, waves, bpc in itertools.product((2, 4), (2, 4, 8, 16, 32), (2, 4, 8),
+                                                   (1, 2, 4, 8, 16)):
+        yield dict(vec_words=vec, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=bpc,
+                   cache_policy=1)
+
+
+def tune_batch(batch, *, candidates=None, cache: TuneCache | None = None, launches=10, reps=3,
+               verbose=False):
+    """Tune the persistent batch launch of a Batch (its table and arenas).
+    Returns (cfg, microseconds per batched launch)."""
+    from .batch import edge_batch
+    kw = dict(batch.kw)
+    kw.pop("cfg", None)
+    edge_batch(batch.inp, batch.out, batch.table_dev, batch.n, batch.workspace, **kw)
+    torch.cuda.synchronize()
+    ref = batch.out.clone()
+    best, best_us, tried = None, float("inf"), 0
+    for c in (list(candidates) if candidates is not None else list(batch_candidates())):
+        batch.out.zero_()
+        edge_batch(batch.inp, batch.out, batch.table_dev, batch.n, batch.workspace, cfg=c, **kw)
+        torch.cuda.synchronize()
+        if not torch.equal(batch.out, ref):
+            if verbose:
+                print("rejected (output differs):", c)
+            continue
+        us = _graph_time_us(lambda: edge_batch(batch.inp, batch.out, batch.table_dev, batch.n,
+                                               batch.workspace, cfg=c, **kw), launches, reps)
+        tried += 1
+        if verbose:
+            print(f"{us:9.2f} us  {c}")
+        if us < best_us:
+            best, best_us = c, us
+    if best is None:
+        raise RuntimeError("no candidate configuration matched the built-in output")
+    if cache is not None:
+        total = int(batch.inp.numel())
+        cache.put(batch_key(batch.n, total, batch.word_bits, kw.get("mode", "masks")), best,
+                  best_us, tried)
+    return best, best_us
+
+
+def lookup_image(height, width, word_bits, mode="masks", cache: TuneCache | None = None):
+    cache = cache or TuneCache()
+    return cache.get(image_key(height, width, word_bits, mode))
+
+
+def lookup_batch(n_images, total_words, word_bits, mode="masks", cache: TuneCache | None = None):
+    cache = cache or TuneCache()
+    return cache.get(batch_key(n_images, total_words, word_bits, mode))
+
+
+def _main(argv=None):
+    """Tune the benchmark's workloads on this GPU and write a table."""
+    import argparse
+    import numpy as np
+    import paper_1401_5245_amd as em
+    ap = argparse.ArgumentParser(description="tune libedgemask launch configurations")
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--verbose", action="store_true")
+    a = ap.parse_args(argv)
+    cache = TuneCache(a.out)
+    rng = np.random.default_rng(a.seed)
+    for (H, W, wb, mode) in ((512, 512, 32, "masks"), (8192, 8192, 64, "masks"),
+                             (16384, 16384, 64, "full"), (65536, 65536, 64, "masks")):
+        words = -(-W // wb) * (wb // 32) * H
+        inp = torch.from_numpy(rng.integers(0, 2**31, size=words, dtype=np.int64)
+                               .astype(np.int32)).cuda()
+        if wb == 64:
+            inp = inp.view(torch.int64)
+        inp = inp.view(H, -1)
+        out = torch.empty_like(inp)
+        cfg, us = tune_image(inp, out, H, W, mode=mode, cache=cache, verbose=a.verbose,
+                             launches=4 if H >= 65536 else 20)
+        print(f"image {H}x{W} B{wb} {mode}: {us:.2f} us  {cfg}", flush=True)
+        del inp, out
+        torch.cuda.empty_cache()
+    from synth import images, pack_rows
+    crops = images.glyph_crops(4096, seed=3)
+    b = em.Batch([(pack_rows(c, 32), c.shape[1]) for c in crops], 32)
+    cfg, us = tune_batch(b, cache=cache, verbose=a.verbose)
+    print(f"batch 4096 crops: {us:.2f} us  {cfg}", flush=True)
+    cache.save(a.out)
+    print("wrote", a.out)
+
+
+if __name__ == "__main__":
+    _main()
+
+
+__all__ = ["TuneCache", "tune_image", "tune_batch", "lookup_image", "lookup_batch",
+           "image_candidates", "batch_candidates", "_abi"]
