@@ -134,18 +134,37 @@ def check_rows(img, out_words, width, rows, border="white", clauses=1):
 
 # ------------------------------------------------------------ workloads ----
 
-def graph_of(torch, launch_all):
-    """Capture launch_all() (a sequence of library launches on the current
-    stream) into a graph; returns the torch.cuda.CUDAGraph."""
+def graph_of(torch, launch_all, nstreams: int = 1, fns=None):
+    """Capture library launches into a graph.
+
+    Either launch_all() issues them all on the current stream, or `fns` is a
+    list of launches dealt round-robin over `nstreams` streams forked from
+    and joined back to the capture stream (independent images may then
+    overlap on the device). Returns the torch.cuda.CUDAGraph."""
+    def issue():
+        if fns is None:
+            launch_all()
+            return
+        cs = torch.cuda.current_stream()
+        side = [torch.cuda.Stream() for _ in range(nstreams - 1)]
+        streams = [cs] + side
+        for s in side:
+            s.wait_stream(cs)
+        for i, f in enumerate(fns):
+            with torch.cuda.stream(streams[i % nstreams]):
+                f()
+        for s in side:
+            cs.wait_stream(s)
+
     g = torch.cuda.CUDAGraph()
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        launch_all()            # warm-up outside capture
-    torch.cuda.current_stream().wait_stream(side)
+    warm = torch.cuda.Stream()
+    warm.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(warm):
+        issue()                 # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(warm)
     torch.cuda.synchronize()
     with torch.cuda.graph(g):
-        launch_all()
+        issue()
     torch.cuda.synchronize()
     return g
 
@@ -167,8 +186,12 @@ def headline(torch, em, tm, steps, warmup):
     exact = bool(np.array_equal(unpack_rows(ref, W), oracle.edge(img)))
     log(f"headline parity vs oracle (whole image): {exact}")
 
+    from paper_1401_5245_amd import tune
+    cfg = tune.lookup_image(H, W, 64, "masks")     # autotuned entry (None: built-in)
+    log(f"launch configuration: {cfg or 'built-in'}")
+
     # eager: one Python call per launch
-    launches = [em.prepare(ins[i], outs[i], H, W) for i in range(NB)]
+    launches = [em.prepare(ins[i], outs[i], H, W, cfg=cfg) for i in range(NB)]
 
     def step(i):
         launches[i % NB]()
@@ -178,26 +201,30 @@ def headline(torch, em, tm, steps, warmup):
     torch.cuda.synchronize()
     eager_ms = tm.per_call_ms(step, steps)
 
-    # graph: the 40 rotating launches captured once, replayed back to back
-    def launch_all():
-        for i in range(NB):
-            em.edge_masks(ins[i], outs[i], H, W)
-
-    for o in outs:
-        o.zero_()
-    g = graph_of(torch, launch_all)
-    for o in outs:
-        o.zero_()
+    # graph: the 40 rotating launches captured once, replayed back to back,
+    # issued on 1, 2 or 4 streams
     reps = max(1, steps // NB)
-    for _ in range(max(1, warmup // NB)):
-        g.replay()
-    torch.cuda.synchronize()
-    ms = tm.per_call_ms(lambda i: g.replay(), reps) / NB
-    replay_ok = all(np.array_equal(o.cpu().numpy().view(np.uint64), ref) for o in outs[::13])
-    log(f"graph replays match the eager output: {replay_ok}")
-    del ins, outs, launches, g
+    per_streams = {}
+    replay_ok = True
+    for ns in (1, 2, 4):
+        for o in outs:
+            o.zero_()
+        fns = [(lambda i=i: em.edge_image(ins[i], outs[i], H, W, cfg=cfg)) for i in range(NB)]
+        g = graph_of(torch, None, nstreams=ns, fns=fns)
+        for o in outs:
+            o.zero_()
+        for _ in range(max(1, warmup // NB)):
+            g.replay()
+        torch.cuda.synchronize()
+        per_streams[ns] = tm.per_call_ms(lambda i: g.replay(), reps) / NB
+        ok = all(np.array_equal(o.cpu().numpy().view(np.uint64), ref) for o in outs[::7])
+        replay_ok &= ok
+        log(f"graph on {ns} stream(s): {per_streams[ns] * 1e3:.2f} us/launch, "
+            f"replays match the eager output: {ok}")
+        del g
+    del ins, outs, launches
     torch.cuda.empty_cache()
-    return img, ms, eager_ms, reps * NB, exact and replay_ok
+    return img, per_streams, eager_ms, reps * NB, exact and replay_ok, cfg
 
 
 def copy_ceiling(torch, em, tm, nbytes, nb, steps):
@@ -309,10 +336,10 @@ def full_16384(torch, em, tm, steps):
 def batched_crops(torch, em, tm, steps):
     from synth import images, pack_rows, unpack_rows
     import oracle
-    from paper_1401_5245_amd import _abi
+    from paper_1401_5245_amd import _abi, tune
     log("generating 4096 glyph crops (seed 3)")
     crops = images.glyph_crops(4096, seed=3)
-    b = em.Batch([(pack_rows(c, 32), c.shape[1]) for c in crops], 32, "cuda")
+    b = em.Batch([(pack_rows(c, 32), c.shape[1]) for c in crops], 32, "cuda", cfg="tuned")
     g = b.graph()
     g.launch()
     torch.cuda.synchronize()
@@ -343,8 +370,8 @@ def batched_crops(torch, em, tm, steps):
             "gpx_s_eager": round(px / (ms_eager * 1e-3) / 1e9, 1),
             "gpx_s_per_image_launches": round(px / (ms_plain * 1e-3) / 1e9, 2),
             "speedup_vs_per_image": round(ms_plain / ms_graph, 1),
-            "us_graph": round(ms_graph * 1e3, 2), "cfg": b.kw["cfg"] or em.default_cfg(
-                0, 0, 32, batch=True),
+            "us_graph": round(ms_graph * 1e3, 2),
+            "cfg": tune.lookup_batch(b.n, b.inp.numel(), 32) or em.default_cfg(0, 0, 32, batch=True),
             "bit_exact_first_256": exact}
 
 
@@ -365,22 +392,30 @@ def serving(torch, em, p99_bound_ms=20.0, budget=4 << 30):
     mean_px = float(pool.pixels.mean())
     srv = Server(pool, budget, max_inflight=3)
     rng = np.random.default_rng(55)
-    out = {"workload": "serving: Poisson arrivals, 64-image pool, sides log-uniform [64,4096], "
-                       "half glyph / half Bernoulli(0.3), uint64; HBM budget %d GiB, 3 batches "
-                       "in flight" % (budget >> 30),
+    out = {"workload": "serving: Poisson arrivals, 64-image pinned ingress ring (sides "
+                       "log-uniform [64,4096], half glyph / half Bernoulli(0.3)), uint64; HBM "
+                       "budget %d GiB, 3 batches in flight; latency = result in host memory "
+                       "- scheduled arrival" % (budget >> 30),
            "mean_mpx_per_request": round(mean_px / 1e6, 3), "p99_bound_ms": p99_bound_ms}
-    for name, per_req, rates in (("batched", False, (5e3, 1e4, 2e4, 4e4, 8e4, 1.6e5)),
-                                 ("per_request", True, (2e3, 5e3, 1e4, 2e4, 4e4))):
+    for name, per_req, rates in (("batched", False, (1e4, 2e4, 4e4, 8e4, 1.2e5, 1.6e5, 2.4e5,
+                                                     3.2e5)),
+                                 ("per_request", True, (2e3, 5e3, 1e4, 1.5e4, 2e4, 3e4))):
         runs, best = [], None
         for rate in rates:
-            n = int(min(max(200, rate * 0.4), 8000))
-            arr = poisson_arrivals(n, rate, seed=int(rate))
-            idx = rng.integers(0, len(pool_imgs), size=n)
-            srv.run(arr[:50], idx[:50], per_request=per_req)          # warm-up
-            st = srv.run(arr, idx, per_request=per_req).summary()
+            n = int(min(max(400, rate * 0.3), 100000))
+            trials = []
+            for trial in range(2):
+                arr = poisson_arrivals(n, rate, seed=int(rate) + trial)
+                # the pool is an ingress ring: consecutive requests are
+                # consecutive pool images (random sizes, random start)
+                idx = (int(rng.integers(0, len(pool_imgs))) + np.arange(n)) % len(pool_imgs)
+                srv.run(arr[:50], idx[:50], per_request=per_req)          # warm-up
+                trials.append(srv.run(arr, idx, per_request=per_req).summary())
+            st = max(trials, key=lambda t: t["p99_ms"])   # the worse of two trials
             st["offered_rps"] = rate
+            st["trials_p99_ms"] = [t["p99_ms"] for t in trials]
             runs.append(st)
-            log(f"serve {name} rate={rate:.0f}/s p50={st['p50_ms']} p99={st['p99_ms']} "
+            log(f"serve {name} rate={rate:.0f}/s p50={st['p50_ms']} p99={st['trials_p99_ms']} "
                 f"gpx_s={st['gpx_s']} batches={st['batches']}")
             if st["p99_ms"] <= p99_bound_ms:
                 best = st
@@ -425,7 +460,11 @@ def main():
     if args.serve_only:
         print(json.dumps(serving(torch, em)), flush=True)
         return
-    img, ms, eager_ms, timed, exact = headline(torch, em, tm, args.steps, args.warmup)
+    img, per_streams, eager_ms, timed, exact, hcfg = headline(torch, em, tm, args.steps,
+                                                              args.warmup)
+    kernel_ms = per_streams[1]                      # one stream: launches do not overlap
+    best_ns = min(per_streams, key=per_streams.get)
+    ms = per_streams[best_ns]
     H = W = 8192
     gpx = H * W / (ms * 1e-3) / 1e9
     nbytes = 2 * H * (W // 64) * 8
@@ -437,11 +476,18 @@ def main():
                                   "8192x8192 binary glyph page (seed 2, ~19% black, 0.5% "
                                   "salt-and-pepper), packed uint64 rows, white border, 40 "
                                   "rotating buffer pairs; steps replayed from one captured "
-                                  "HIP graph of the 40 launches",
+                                  "HIP graph of the 40 launches issued on %d stream(s)" % best_ns,
+                      "launch_cfg": hcfg or "built-in",
                       "pixels_per_step": H * W, "bytes_per_step": nbytes},
-           "roofline": roofline(nbytes, ms, measured_traffic()), "bit_exact": exact,
+           "roofline": dict(roofline(nbytes, kernel_ms, measured_traffic()),
+                            timing="single-stream graph replay: each launch runs alone, so the "
+                                   "per-launch time is the kernel's own duration"),
+           "bit_exact": exact,
            "eager_python_loop": {"ms_per_step": round(eager_ms, 5),
-                                 "gpx_s": round(H * W / (eager_ms * 1e-3) / 1e9, 1)}}
+                                 "gpx_s": round(H * W / (eager_ms * 1e-3) / 1e9, 1)},
+           "graph_streams": {str(k): {"ms_per_step": round(v, 5),
+                                      "gpx_s": round(H * W / (v * 1e-3) / 1e9, 1)}
+                             for k, v in per_streams.items()}}
     if not args.no_cpu and not args.headline_only:
         log("timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline(img, args.cpu_seconds)

@@ -61,12 +61,21 @@ def _image_args(inp: torch.Tensor, out: torch.Tensor, height: int, width: int,
     return wb, int(stride_words)
 
 
+def _resolve_cfg(cfg, height, width, word_bits, mode):
+    """None / a dict / an EdgeLaunchCfg, or "tuned": the autotuned entry for
+    this shape class (None when the table has none)."""
+    if isinstance(cfg, str):
+        if cfg != "tuned":
+            raise ValueError(f"unknown cfg {cfg!r}")
+        from . import tune
+        cfg = tune.lookup_image(height, width, word_bits, mode)
+    if cfg is None or isinstance(cfg, EdgeLaunchCfg):
+        return cfg
+    return EdgeLaunchCfg.from_dict(cfg)
+
+
 def _cfg_ptr(cfg):
-    if cfg is None:
-        return None
-    if isinstance(cfg, dict):
-        cfg = EdgeLaunchCfg.from_dict(cfg)
-    return ctypes.byref(cfg)
+    return None if cfg is None else ctypes.byref(cfg)
 
 
 def edge_masks(inp: torch.Tensor, out: torch.Tensor, height: int, width: int, *,
@@ -92,11 +101,13 @@ def edge_full(inp: torch.Tensor, out: torch.Tensor, height: int, width: int, *,
 def edge_image(inp: torch.Tensor, out: torch.Tensor, height: int, width: int, *,
                mode: str = "masks", border: str = "white", clause2_only: bool = False,
                invert: bool = False, cfg=None, stride_words=None, stream=None) -> torch.Tensor:
-    """Single image with explicit mode, flags and launch configuration."""
+    """Single image with explicit mode, flags and launch configuration
+    (cfg: None = built-in, "tuned" = autotuned table entry, or a dict)."""
     wb, s = _image_args(inp, out, height, width, stride_words)
     flags = (EDGE_FLAG_CLAUSE2_ONLY if clause2_only else 0) | (EDGE_FLAG_INVERT_OUT if invert else 0)
+    c = _resolve_cfg(cfg, height, width, wb, mode)
     check(_lib.edge_image_launch(inp.data_ptr(), out.data_ptr(), height, width, s, wb,
-                                 BORDERS[border], MODES[mode], flags, _cfg_ptr(cfg),
+                                 BORDERS[border], MODES[mode], flags, _cfg_ptr(c),
                                  stream_handle(stream)))
     return out
 
@@ -116,9 +127,9 @@ def prepare(inp: torch.Tensor, out: torch.Tensor, height: int, width: int, *,
     must stay alive while the callable is used."""
     wb, s = _image_args(inp, out, height, width, stride_words)
     flags = (EDGE_FLAG_CLAUSE2_ONLY if clause2_only else 0) | (EDGE_FLAG_INVERT_OUT if invert else 0)
-    c = None if cfg is None else (EdgeLaunchCfg.from_dict(cfg) if isinstance(cfg, dict) else cfg)
+    c = _resolve_cfg(cfg, height, width, wb, mode)
     args = (inp.data_ptr(), out.data_ptr(), height, width, s, wb, BORDERS[border], MODES[mode],
-            flags, None if c is None else ctypes.byref(c), stream_handle(stream))
+            flags, _cfg_ptr(c), stream_handle(stream))
     fn = _lib.edge_image_launch
 
     def launch():

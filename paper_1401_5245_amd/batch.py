@@ -41,6 +41,16 @@ def _cfg_ptr(cfg):
     return ctypes.byref(cfg)
 
 
+def _resolve(cfg, n_images, arena_words, word_bits, mode):
+    """cfg "tuned": the autotuned batch entry for this size class (or None)."""
+    if isinstance(cfg, str):
+        if cfg != "tuned":
+            raise ValueError(f"unknown cfg {cfg!r}")
+        from . import tune
+        return tune.lookup_batch(n_images, arena_words, word_bits, mode)
+    return cfg
+
+
 def _word_bits(t: torch.Tensor) -> int:
     from . import word_bits_of
     return word_bits_of(t)
@@ -99,6 +109,7 @@ def edge_batch(in_arena: torch.Tensor, out_arena: torch.Tensor, table_dev: torch
     wb = _word_bits(in_arena)
     if out_arena.dtype != in_arena.dtype or out_arena.numel() != in_arena.numel():
         raise ValueError("input and output arenas must match in type and size")
+    cfg = _resolve(cfg, n_images, in_arena.numel(), wb, mode)
     check(_lib.edge_batch(in_arena.data_ptr(), out_arena.data_ptr(), in_arena.numel(),
                           table_dev.data_ptr(), n_images, wb, _BORDERS[border], _MODES[mode],
                           _flags(clause2_only, invert), _cfg_ptr(cfg), workspace.data_ptr(),
@@ -116,6 +127,7 @@ class BatchGraph:
     def __init__(self, in_arena, out_arena, table_dev, n_images, workspace, *,
                  border="white", mode="masks", clause2_only=False, invert=False, cfg=None):
         wb = _word_bits(in_arena)
+        cfg = _resolve(cfg, n_images, in_arena.numel(), wb, mode)
         self._keep = (in_arena, out_arena, table_dev, workspace)
         h = ctypes.c_void_p()
         check(_lib.edge_batch_graph_create(

@@ -265,8 +265,9 @@ int alignment_words(uintptr_t p) {
 }
 
 // Built-in single-image shape. Rows of <= 32 words: narrow units of up to
-// 16 steps. Wider rows: about 2048 strips (8 per compute unit), each at
-// least 2 and at most 256 rows tall.
+// 16 steps. Wider rows: about 2048 strips (8 wavefronts per compute unit,
+// one workgroup of 8 each when there are enough rows), each at least 2 and
+// at most 256 rows tall.
 edge_launch_cfg default_single(int64_t height, int64_t wd32) {
     edge_launch_cfg c;
     c.blocks_per_cu = 1;
@@ -281,14 +282,14 @@ edge_launch_cfg default_single(int64_t height, int64_t wd32) {
         const int v = pick_vw(wd32, 4, 0, 0);
         const int64_t chunks = ceil_div(wd32, (int64_t)kWave * v);
         c.rows_per_tile = (int32_t)pow2_floor(std::max<int64_t>(2, std::min<int64_t>(256, chunks * height / 2048)));
-        c.waves_per_block = c.rows_per_tile >= 16 ? 8 : 4;
+        c.waves_per_block = c.rows_per_tile >= 64 ? 8 : 4;
     }
     return c;
 }
 
-// Streaming (non-temporal) loads and stores pay off once an image's
-// traffic no longer fits comfortably in the last-level cache.
-constexpr int64_t kStreamBytes = 48ll << 20;
+// Streaming (non-temporal) loads and stores pay off from a few MiB of
+// traffic up (measured: 16 MiB and larger); small images stay cached.
+constexpr int64_t kStreamBytes = 8ll << 20;
 
 edge_launch_cfg default_batch() {
     edge_launch_cfg c;

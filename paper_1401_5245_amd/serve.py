@@ -202,7 +202,17 @@ class Server:
             record_outputs: bool = False) -> Stats:
         """Serve requests r = 0..n-1 arriving at `arrivals[r]` seconds with
         image pool_index[r]. Blocks until every request is answered."""
+        import gc
         import paper_1401_5245_amd as em
+        gc_was_enabled = gc.isenabled()
+        gc.disable()            # no collector pauses inside the serving loop
+        try:
+            return self._run(em, arrivals, pool_index, per_request, record_outputs)
+        finally:
+            if gc_was_enabled:
+                gc.enable()
+
+    def _run(self, em, arrivals, pool_index, per_request, record_outputs) -> Stats:
         pool = self.pool
         n = len(arrivals)
         reqs = [Request(i, int(pool_index[i]), float(arrivals[i])) for i in range(n)]

@@ -43,7 +43,8 @@ def test_results_same_alone_and_in_mix(per_request, budget_kib):
     arrivals = poisson_arrivals(n, 20000.0, seed=1)
     idx = np.random.default_rng(2).integers(0, len(imgs), size=n)
     budget = budget_kib << 10
-    need = max(pool.words(i) for i in range(len(imgs))) * 8 * 2
+    maxw = max(pool.words(i) for i in range(len(imgs)))
+    need = (maxw + maxw % 2) * 8 * 2          # blocks are rounded to 16 bytes
     if need > budget:   # keep every request servable under the small budget
         budget = need
     srv = Server(pool, budget, max_inflight=3)
