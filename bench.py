@@ -476,7 +476,7 @@ def main():
                                   "8192x8192 binary glyph page (seed 2, ~19% black, 0.5% "
                                   "salt-and-pepper), packed uint64 rows, white border, 40 "
                                   "rotating buffer pairs; steps replayed from one captured "
-                                  "HIP graph of the 40 launches issued on %d stream(s)" % best_ns,
+                                  f"HIP graph of the 40 launches issued on {best_ns} stream(s)",
                       "launch_cfg": hcfg or "built-in",
                       "pixels_per_step": H * W, "bytes_per_step": nbytes},
            "roofline": dict(roofline(nbytes, kernel_ms, measured_traffic()),
