@@ -44,6 +44,10 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--serve-only", action="store_true",
                    help="run only the serving sweep (prints its JSON)")
+    p.add_argument("--batch-only", action="store_true",
+                   help="run only the batched-crops workload (prints its JSON)")
+    p.add_argument("--streams", default="1,2,4",
+                   help="stream counts the headline graph is captured with")
     return p.parse_args()
 
 
@@ -169,7 +173,7 @@ def graph_of(torch, launch_all, nstreams: int = 1, fns=None):
     return g
 
 
-def headline(torch, em, tm, steps, warmup):
+def headline(torch, em, tm, steps, warmup, stream_counts=(1, 2, 4)):
     from synth import images, pack_rows, unpack_rows
     import oracle
     H = W = 8192
@@ -206,7 +210,7 @@ def headline(torch, em, tm, steps, warmup):
     reps = max(1, steps // NB)
     per_streams = {}
     replay_ok = True
-    for ns in (1, 2, 4):
+    for ns in stream_counts:
         for o in outs:
             o.zero_()
         fns = [(lambda i=i: em.edge_image(ins[i], outs[i], H, W, cfg=cfg)) for i in range(NB)]
@@ -250,12 +254,13 @@ def plain_512(torch, em, tm, steps):
     words = pack_rows(img, 32)
     inp = words_tensor(torch, words)
     out = torch.empty_like(inp)
-    em.edge_masks(inp, out, 512, 512)
+    em.edge_image(inp, out, 512, 512, cfg="tuned")
     torch.cuda.synchronize()
     exact = bool(np.array_equal(unpack_rows(out.cpu().numpy().view(np.uint32), 512),
                                 oracle.edge(img)))
     NL = 50
-    g = graph_of(torch, lambda: [em.edge_masks(inp, out, 512, 512) for _ in range(NL)])
+    g = graph_of(torch, lambda: [em.edge_image(inp, out, 512, 512, cfg="tuned")
+                                 for _ in range(NL)])
     for _ in range(3):
         g.replay()
     reps = max(1, steps // NL)
@@ -277,7 +282,7 @@ def plain_65536(torch, em, tm, steps):
     inp = words_tensor(torch, words)
     del words
     out = torch.empty_like(inp)
-    em.edge_masks(inp, out, H, W)
+    em.edge_image(inp, out, H, W, cfg="tuned")
     torch.cuda.synchronize()
     # image row y is tile row y % 8192 repeated 8 times across
     ok = True
@@ -288,8 +293,8 @@ def plain_65536(torch, em, tm, steps):
         got = unpack_rows(out[r:r + 1].cpu().numpy().view(np.uint64), W)[0]
         ok &= bool(np.array_equal(got, want))
     for _ in range(3):
-        em.edge_masks(inp, out, H, W)
-    ms = tm.per_call_ms(lambda i: em.edge_masks(inp, out, H, W), steps)
+        em.edge_image(inp, out, H, W, cfg="tuned")
+    ms = tm.per_call_ms(lambda i: em.edge_image(inp, out, H, W, cfg="tuned"), steps)
     nbytes = 2 * H * (W // 64) * 8
     del inp, out
     torch.cuda.empty_cache()
@@ -310,7 +315,7 @@ def full_16384(torch, em, tm, steps):
     ins = [src.clone() for _ in range(NB)]
     outs = [torch.empty_like(src) for _ in range(NB)]
     rows = np.array([0, 1, 2, 777, 8191, 8192, 12345, 16382, 16383])
-    em.edge_full(ins[0], outs[0], H, W)
+    em.edge_image(ins[0], outs[0], H, W, mode="full", cfg="tuned")
     torch.cuda.synchronize()
     ok = check_rows(img, outs[0].cpu().numpy().view(np.uint64), W, rows, clauses=3)
     em.edge_full(ins[0], outs[0], H, W, clause2_only=True)
@@ -318,7 +323,8 @@ def full_16384(torch, em, tm, steps):
     c2 = outs[0].cpu().numpy().view(np.uint64)
     ok2 = check_rows(img, c2, W, rows, clauses=2)
     n_c2 = int(sum(int(v).bit_count() for v in c2[rows].reshape(-1)))
-    g = graph_of(torch, lambda: [em.edge_full(ins[i], outs[i], H, W) for i in range(NB)])
+    g = graph_of(torch, lambda: [em.edge_image(ins[i], outs[i], H, W, mode="full", cfg="tuned")
+                                 for i in range(NB)])
     g.replay()
     reps = max(1, steps // NB)
     ms = tm.per_call_ms(lambda i: g.replay(), reps) / NB
@@ -397,8 +403,8 @@ def serving(torch, em, p99_bound_ms=20.0, budget=4 << 30):
                        "budget %d GiB, 3 batches in flight; latency = result in host memory "
                        "- scheduled arrival" % (budget >> 30),
            "mean_mpx_per_request": round(mean_px / 1e6, 3), "p99_bound_ms": p99_bound_ms}
-    for name, per_req, rates in (("batched", False, (1e4, 2e4, 4e4, 8e4, 1.2e5, 1.6e5, 2.4e5,
-                                                     3.2e5)),
+    for name, per_req, rates in (("batched", False, (1e4, 2e4, 4e4, 8e4, 1.6e5, 2.4e5, 3.2e5,
+                                                     4.8e5, 6.4e5)),
                                  ("per_request", True, (2e3, 5e3, 1e4, 1.5e4, 2e4, 3e4))):
         runs, best = [], None
         for rate in rates:
@@ -460,8 +466,12 @@ def main():
     if args.serve_only:
         print(json.dumps(serving(torch, em)), flush=True)
         return
+    if args.batch_only:
+        print(json.dumps(batched_crops(torch, em, tm, args.steps)), flush=True)
+        return
+    counts = tuple(sorted({1} | {int(v) for v in args.streams.split(",")}))
     img, per_streams, eager_ms, timed, exact, hcfg = headline(torch, em, tm, args.steps,
-                                                              args.warmup)
+                                                              args.warmup, counts)
     kernel_ms = per_streams[1]                      # one stream: launches do not overlap
     best_ns = min(per_streams, key=per_streams.get)
     ms = per_streams[best_ns]

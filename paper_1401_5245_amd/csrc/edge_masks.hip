@@ -282,7 +282,7 @@ edge_launch_cfg default_single(int64_t height, int64_t wd32) {
         const int v = pick_vw(wd32, 4, 0, 0);
         const int64_t chunks = ceil_div(wd32, (int64_t)kWave * v);
         c.rows_per_tile = (int32_t)pow2_floor(std::max<int64_t>(2, std::min<int64_t>(256, chunks * height / 2048)));
-        c.waves_per_block = c.rows_per_tile >= 64 ? 8 : 4;
+        c.waves_per_block = c.rows_per_tile >= 16 ? 8 : 4;
     }
     return c;
 }
