@@ -378,34 +378,37 @@ __device__ __forceinline__ void narrow_unit(const Geom& g, int ya, int yb, uint3
 __host__ __device__ inline int pick_vw(int64_t wd, int vmax, int64_t offset_words,
                                        int64_t stride_words) {
     int v = vmax;
-    while (v > 1 && ((offset_words % v) != 0 || (stride_words % v) != 0 || wd < 32 * v)) v /= 2;
+    while (v > 1 && ((offset_words & (v - 1)) != 0 || (stride_words & (v - 1)) != 0 ||
+                     wd < 32 * v))
+        v /= 2;
     return v;
 }
 
-// Work units of one image (0 for an empty image).
+// Work units of one image (0 for an empty image). All quotients fit 32 bits
+// (height < 2^31, wd < 2^26, band <= 64 * 1024), so they use 32-bit division.
 struct UnitShape {
-    int narrow;       // 1: narrow units, 0: strips
-    int vw;           // strip vector width
-    int64_t chunks;   // strips: word chunks per row
-    int64_t band;     // rows per unit
-    int64_t count;    // units
+    int narrow;        // 1: narrow units, 0: strips
+    int vw;            // strip vector width
+    uint32_t chunks;   // word chunks per row (1 for narrow units)
+    uint32_t band;     // rows per unit
+    int64_t count;     // units
 };
 
 __host__ __device__ inline UnitShape unit_shape(int64_t height, int64_t width, int64_t wd,
                                                 int64_t offset_words, int64_t stride_words,
                                                 int vmax, int rows) {
-    UnitShape s{0, 1, 0, 1, 0};
+    UnitShape s{0, 1, 1, 1, 0};
     if (height <= 0 || width <= 0) return s;
     if (wd <= kNarrowMaxWords) {
         s.narrow = 1;
-        s.band = (int64_t)(kWave / wd) * rows;
-        s.chunks = 1;
+        s.band = (uint32_t)(kWave / wd) * (uint32_t)rows;
     } else {
         s.vw = pick_vw(wd, vmax, offset_words, stride_words);
-        s.chunks = (wd + (int64_t)kWave * s.vw - 1) / ((int64_t)kWave * s.vw);
-        s.band = rows;
+        const uint32_t span = (uint32_t)kWave * (uint32_t)s.vw;
+        s.chunks = ((uint32_t)wd - 1u) / span + 1u;
+        s.band = (uint32_t)rows;
     }
-    s.count = s.chunks * ((height + s.band - 1) / s.band);
+    s.count = (int64_t)s.chunks * (int64_t)(((uint32_t)height - 1u) / s.band + 1u);
     return s;
 }
 

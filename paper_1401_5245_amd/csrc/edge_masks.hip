@@ -47,96 +47,157 @@ __global__ void __launch_bounds__(512) k_narrow(Geom g, int64_t band, int64_t nu
     narrow_unit<MODE>(g, (int)ya, (int)yb, bw, invert != 0);
 }
 
-// Descriptor check shared by the host validator and the device planner.
+// Descriptor check shared by the host validator and the device planner:
+// sizes and offset non-negative, stride >= the row's words, and every word
+// of the image inside the arena. Division-free for strides below 2^32.
 __host__ __device__ static inline bool desc_ok(const edge_image_desc& d, int64_t arena_words,
                                                int word_bits) {
     if (d.height < 0 || d.width < 0 || d.offset_words < 0 || d.stride_words < 0) return false;
     if (d.height == 0 || d.width == 0) return true;
-    const int64_t wd = ((int64_t)d.width + word_bits - 1) / word_bits;
-    if (d.stride_words < wd || wd > arena_words) return false;
+    const int shift = word_bits == 64 ? 6 : 5;
+    const int64_t wd = ((int64_t)d.width + word_bits - 1) >> shift;
+    if (d.stride_words < wd || wd > arena_words || d.offset_words > arena_words) return false;
+    if (d.stride_words < (1ll << 32)) {
+        const int64_t span = (int64_t)(d.height - 1) * d.stride_words + wd;   // < 2^63
+        return span <= arena_words - d.offset_words;
+    }
     if ((int64_t)(d.height - 1) > (arena_words - wd) / d.stride_words) return false;
     const int64_t span = (int64_t)(d.height - 1) * d.stride_words + wd;
     return d.offset_words <= arena_words - span;
 }
 
-// Workspace layout (int64 words): [0] total units, [1] skipped descriptors,
-// [2..7] reserved, [8 + i] first unit of image i (i = 0..n; [8 + n] = total).
+// Workspace layout: int64 words [0] total units, [1] skipped descriptors,
+// [2..7] reserved, [8 + i] first unit of image i (i = 0..n; [8 + n] = total);
+// then, 8-byte aligned, int32 first_image[b] for every persistent workgroup
+// b < kMaxBatchBlocks: the image holding that workgroup's first unit.
 constexpr int kWsHeader = 8;
+constexpr int kMaxBatchBlocks = 65536;
+constexpr int kPlanThreads = 1024;
 
-// Batch planner: one workgroup of 1024 threads counts the work units of
-// every image and writes their exclusive prefix sum.
-__global__ void __launch_bounds__(1024) k_plan(const edge_image_desc* tab, int n,
-                                               int64_t arena_words, int word_bits, int vmax,
-                                               int rows, int64_t* ws) {
-    __shared__ int64_t wave_sum[16];
+__host__ __device__ inline int64_t ws_block_map_offset(int32_t n) { return kWsHeader + (int64_t)n + 1; }
+
+// Units of descriptor d (0 when it fails the checks; *bad counts those).
+__device__ __forceinline__ int64_t desc_units(const edge_image_desc& d, int64_t arena_words,
+                                              int word_bits, int vmax, int rows, int* bad) {
+    if (!desc_ok(d, arena_words, word_bits)) {
+        ++*bad;
+        return 0;
+    }
+    const int per = word_bits / 32;
+    const int shift = word_bits == 64 ? 6 : 5;
+    const int64_t wd = (((int64_t)d.width + word_bits - 1) >> shift) * per;
+    return unit_shape(d.height, d.width, wd, d.offset_words * per, d.stride_words * per, vmax,
+                      rows).count;
+}
+
+// Batch planner: one workgroup; thread t owns the contiguous images
+// [t*per, (t+1)*per). It counts their work units (the first kKeep counts
+// stay in registers), one workgroup scan turns the chunk sums into each
+// image's first unit, and each thread then records, for the persistent
+// workgroups whose first unit falls inside its chunk, which image holds it
+// (workgroup b's first unit is floor(total * b / nblocks)).
+constexpr int kKeep = 8;
+
+__global__ void __launch_bounds__(kPlanThreads) k_plan(const edge_image_desc* tab, int n,
+                                                       int64_t arena_words, int word_bits,
+                                                       int vmax, int rows, int nblocks,
+                                                       int64_t* ws) {
+    __shared__ int64_t wave_sum[kPlanThreads / kWave];
     __shared__ int bad_count;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const int nwaves = blockDim.x / kWave;
-    const int per = word_bits / 32;
+    const int per = (n + kPlanThreads - 1) / kPlanThreads;
+    const int i0 = min(n, tid * per), i1 = min(n, i0 + per);
     int64_t* start = ws + kWsHeader;
+    int32_t* block_image = reinterpret_cast<int32_t*>(ws + ws_block_map_offset(n));
     if (tid == 0) bad_count = 0;
     __syncthreads();
-    int64_t carry = 0;
-    for (int base = 0; base < n; base += blockDim.x) {
-        const int i = base + tid;
-        int64_t cnt = 0;
-        if (i < n) {
-            const edge_image_desc d = tab[i];
-            if (desc_ok(d, arena_words, word_bits)) {
-                const int64_t wd = ((int64_t)d.width + word_bits - 1) / word_bits * per;
-                cnt = unit_shape(d.height, d.width, wd, d.offset_words * per,
-                                 d.stride_words * per, vmax, rows).count;
-            } else {
-                atomicAdd(&bad_count, 1);
+
+    int bad = 0;
+    int64_t mine = 0;
+    int64_t cnt[kKeep];
+#pragma unroll
+    for (int k = 0; k < kKeep; ++k) {
+        cnt[k] = i0 + k < i1 ? desc_units(tab[i0 + k], arena_words, word_bits, vmax, rows, &bad)
+                             : 0;
+        mine += cnt[k];
+    }
+    for (int i = i0 + kKeep; i < i1; ++i)
+        mine += desc_units(tab[i], arena_words, word_bits, vmax, rows, &bad);
+    if (bad) atomicAdd(&bad_count, bad);
+
+    int64_t x = mine;                                  // inclusive scan of the chunk sums
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int64_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == kWave - 1) wave_sum[wave] = x;
+    __syncthreads();
+    int64_t before = 0, total = 0;
+    for (int w = 0; w < kPlanThreads / kWave; ++w) {
+        const int64_t v = wave_sum[w];
+        if (w < wave) before += v;
+        total += v;
+    }
+    const int64_t u_first = before + x - mine;         // first unit of image i0
+
+    int unused = 0;
+    int64_t u = u_first;
+#pragma unroll
+    for (int k = 0; k < kKeep; ++k) {
+        if (i0 + k < i1) start[i0 + k] = u;
+        u += cnt[k];
+    }
+    for (int i = i0 + kKeep; i < i1; ++i) {
+        start[i] = u;
+        u += desc_units(tab[i], arena_words, word_bits, vmax, rows, &unused);
+    }
+
+    if (mine > 0) {
+        // workgroups b with floor(total*b/nblocks) in [u_first, u_first + mine)
+        const int64_t b_lo = (u_first * nblocks + total - 1) / total;
+        const int64_t b_hi = min((int64_t)nblocks, ((u_first + mine) * nblocks + total - 1) / total);
+        int i = i0;
+        int64_t s_i = u_first;                            // first unit of image i
+        for (int64_t b = b_lo; b < b_hi; ++b) {
+            const int64_t ub = total * b / nblocks;
+            for (;;) {
+                const int k = i - i0;
+                int64_t c = 0;
+#pragma unroll
+                for (int q = 0; q < kKeep; ++q) c = (q == k) ? cnt[q] : c;
+                if (k >= kKeep) c = desc_units(tab[i], arena_words, word_bits, vmax, rows, &unused);
+                if (ub < s_i + c) break;
+                s_i += c;
+                ++i;
             }
+            block_image[b] = i;
         }
-        int64_t x = cnt;
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int64_t y = __shfl_up(x, off);
-            if (lane >= off) x += y;
-        }
-        if (lane == kWave - 1) wave_sum[wave] = x;
-        __syncthreads();
-        int64_t before = 0, total = 0;
-        for (int w = 0; w < nwaves; ++w) {
-            const int64_t s = wave_sum[w];
-            if (w < wave) before += s;
-            total += s;
-        }
-        if (i < n) start[i] = carry + before + x - cnt;
-        carry += total;
-        __syncthreads();
     }
     if (tid == 0) {
-        start[n] = carry;
-        ws[0] = carry;
-        ws[1] = bad_count;
+        start[n] = total;
+        ws[0] = total;
+        ws[1] = bad_count;     // every atomicAdd precedes the scan's barrier
     }
 }
 
 // Persistent batch kernel: wavefront gw of nw processes the contiguous unit
-// range [total*gw/nw, total*(gw+1)/nw) across the images of the table.
+// range [total*gw/nw, total*(gw+1)/nw) across the images of the table; its
+// first image comes from its workgroup's entry of the planner's map.
 template <int MODE>
 __global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out,
                                                const edge_image_desc* tab, int n, int word_bits,
                                                const int64_t* ws, int vmax, int rows, uint32_t bw,
                                                int invert) {
     const int wpb = blockDim.x / kWave;
+    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t nw = (int64_t)gridDim.x * wpb;
-    const int64_t gw = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
-                       wave_uniform(threadIdx.x / kWave);
+    const int64_t gw = (int64_t)lb * wpb + wave_uniform(threadIdx.x / kWave);
     const int64_t total = ws[0];
     const int64_t* start = ws + kWsHeader;
     const int64_t u0 = total * gw / nw;
     const int64_t u1 = total * (gw + 1) / nw;
     if (u0 >= u1) return;
-    // Image holding unit u0: the largest i with start[i] <= u0.
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= u0) lo = mid; else hi = mid - 1;
-    }
-    int i = lo;
+    int i = reinterpret_cast<const int32_t*>(ws + ws_block_map_offset(n))[lb];
     const int per = word_bits / 32;
     for (int64_t u = u0; u < u1; ++u) {
         while (start[i + 1] <= u) ++i;
@@ -453,11 +514,11 @@ int batch_enqueue(const BatchArgs& a, hipStream_t s) {
     int vmax = a.cfg.vec_words;
     vmax = std::min(vmax, alignment_words((uintptr_t)a.in));
     vmax = std::min(vmax, alignment_words((uintptr_t)a.out));
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, a.table, a.n, a.arena_words,
-                       a.word_bits, vmax, a.cfg.rows_per_tile, (int64_t*)a.ws);
+    const int blocks = std::min(a.cfg.blocks_per_cu * cus, kMaxBatchBlocks);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, a.table, a.n, a.arena_words,
+                       a.word_bits, vmax, a.cfg.rows_per_tile, blocks, (int64_t*)a.ws);
     rc = launch_status();
     if (rc) return rc;
-    const int blocks = a.cfg.blocks_per_cu * cus;
     switch (kernel_mode(a.mode, a.flags)) {
         case kModePlain: return launch_batch_kernel<kModePlain>(a, vmax, blocks, s);
         case kModeFull: return launch_batch_kernel<kModeFull>(a, vmax, blocks, s);
@@ -523,7 +584,7 @@ int edge_default_cfg(int64_t height, int64_t width, int word_bits, int mode, int
 
 int64_t edge_batch_workspace_bytes(int32_t n_images) {
     if (n_images < 0) return EDGE_ERR_INVALID;
-    return (int64_t)(kWsHeader + (int64_t)n_images + 1) * 8;
+    return ws_block_map_offset(n_images) * 8 + (int64_t)kMaxBatchBlocks * 4;
 }
 
 int edge_batch_check(const edge_image_desc* table_host, int32_t n_images, int64_t arena_words,

@@ -114,7 +114,7 @@ def test_batch_check():
 
 def test_batch_validation():
     need = lib.edge_batch_workspace_bytes(4)
-    assert need == (8 + 5) * 8
+    assert need == (8 + 5) * 8 + 65536 * 4
     assert lib.edge_batch_workspace_bytes(-1) < 0
     W = 0x30000000
 
