@@ -109,16 +109,32 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan(const edge_image_desc* ta
     const int i0 = min(n, tid * per), i1 = min(n, i0 + per);
     int64_t* start = ws + kWsHeader;
     int32_t* block_image = reinterpret_cast<int32_t*>(ws + ws_block_map_offset(n));
+    if (n == 0) {               // nothing to plan (a graph may be captured with n = 0)
+        if (tid == 0) {
+            ws[0] = 0;
+            ws[1] = 0;
+            start[0] = 0;
+        }
+        return;
+    }
     if (tid == 0) bad_count = 0;
     __syncthreads();
 
+    // All descriptor loads first (clamped indices, no branches), then the
+    // arithmetic, so the loads overlap instead of completing one by one.
+    edge_image_desc dd[kKeep];
+#pragma unroll
+    for (int k = 0; k < kKeep; ++k) dd[k] = tab[min(i0 + k, n - 1)];
     int bad = 0;
     int64_t mine = 0;
     int64_t cnt[kKeep];
 #pragma unroll
     for (int k = 0; k < kKeep; ++k) {
-        cnt[k] = i0 + k < i1 ? desc_units(tab[i0 + k], arena_words, word_bits, vmax, rows, &bad)
-                             : 0;
+        int b = 0;
+        const int64_t c = desc_units(dd[k], arena_words, word_bits, vmax, rows, &b);
+        const bool mine_k = i0 + k < i1;
+        cnt[k] = mine_k ? c : 0;
+        bad += mine_k ? b : 0;
         mine += cnt[k];
     }
     for (int i = i0 + kKeep; i < i1; ++i)
