@@ -86,8 +86,12 @@ enum { EDGE_MODE_MASKS = 0, EDGE_MODE_FULL = 1 };
 
 /* Flags. CLAUSE2_ONLY (full mode only): output the black pixels with at
  * most one black 8-neighbour, without clause 1. INVERT_OUT: the display
- * polarity of section 5 (edge pixels 0, others 1); padding bits stay 0. */
-enum { EDGE_FLAG_CLAUSE2_ONLY = 1u << 0, EDGE_FLAG_INVERT_OUT = 1u << 1 };
+ * polarity of section 5 (edge pixels 0, others 1); padding bits stay 0.
+ * PLANNED (batch calls only): the workspace already holds the plan that
+ * edge_batch_plan made for this table, arenas, word size and cfg, so the
+ * device planner is skipped. */
+enum { EDGE_FLAG_CLAUSE2_ONLY = 1u << 0, EDGE_FLAG_INVERT_OUT = 1u << 1,
+       EDGE_FLAG_PLANNED = 1u << 2 };
 
 /* One image of a batch. Offsets and strides count B-bit words from the
  * start of the arena; in and out arenas share the same descriptors. */
@@ -151,6 +155,23 @@ int64_t edge_batch_workspace_bytes(int32_t n_images);
  * arena. Returns EDGE_OK or EDGE_ERR_INVALID. */
 int edge_batch_check(const edge_image_desc* table_host, int32_t n_images,
                      int64_t arena_words, int word_bits);
+
+/* Host-side work plan for a batch: writes into plan_host (>=
+ * edge_batch_workspace_bytes(n_images) bytes, 8-byte aligned, host memory)
+ * the plan the device planner would write for table_host, and the number
+ * of leading bytes that matter in *plan_used_bytes. The caller copies those
+ * bytes into the device workspace and calls edge_batch with
+ * EDGE_FLAG_PLANNED. in_arena/out_arena are the device arenas (only their
+ * alignment is read) and cfg must equal the one given to edge_batch.
+ * Returns EDGE_ERR_INVALID when a descriptor fails edge_batch_check. Makes
+ * one HIP query (the compute-unit count, cached). The batch kernel checks
+ * the plan's header and every unit against its image, so a plan that does
+ * not belong to the table gives wrong output but no access outside valid
+ * images of the arenas. */
+int edge_batch_plan(const void* in_arena, const void* out_arena, int64_t arena_words,
+                    const edge_image_desc* table_host, int32_t n_images, int word_bits,
+                    const edge_launch_cfg* cfg, void* plan_host, int64_t plan_bytes,
+                    int64_t* plan_used_bytes);
 
 /* Many independent images in one persistent launch (each image as in
  * edge_masks / edge_full; no bits cross between images).

@@ -25,6 +25,7 @@ EDGE_MODE_MASKS = 0
 EDGE_MODE_FULL = 1
 EDGE_FLAG_CLAUSE2_ONLY = 1 << 0
 EDGE_FLAG_INVERT_OUT = 1 << 1
+EDGE_FLAG_PLANNED = 1 << 2
 
 c_i32, c_i64, c_u32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p
 
@@ -75,6 +76,9 @@ _SIGNATURES = {
     "edge_batch": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i32, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_int, c_u32, ctypes.POINTER(EdgeLaunchCfg), c_vp, c_i64,
                                   c_vp]),
+    "edge_batch_plan": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i32, ctypes.c_int,
+                                       ctypes.POINTER(EdgeLaunchCfg), c_vp, c_i64,
+                                       ctypes.POINTER(c_i64)]),
     "edge_batch_graph_create": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i32, ctypes.c_int,
                                                ctypes.c_int, ctypes.c_int, c_u32,
                                                ctypes.POINTER(EdgeLaunchCfg), c_vp, c_i64,

@@ -14,8 +14,8 @@ import ctypes
 import numpy as np
 import torch
 
-from ._abi import (EDGE_FLAG_CLAUSE2_ONLY, EDGE_FLAG_INVERT_OUT, EdgeImageDesc, EdgeLaunchCfg,
-                   check, load)
+from ._abi import (EDGE_FLAG_CLAUSE2_ONLY, EDGE_FLAG_INVERT_OUT, EDGE_FLAG_PLANNED,
+                   EdgeImageDesc, EdgeLaunchCfg, check, load)
 
 _lib = load()
 
@@ -29,8 +29,9 @@ _NP_WORDS = {32: np.uint32, 64: np.uint64}
 _TORCH_WORDS = {32: torch.int32, 64: torch.int64}
 
 
-def _flags(clause2_only: bool, invert: bool) -> int:
-    return (EDGE_FLAG_CLAUSE2_ONLY if clause2_only else 0) | (EDGE_FLAG_INVERT_OUT if invert else 0)
+def _flags(clause2_only: bool, invert: bool, planned: bool = False) -> int:
+    return ((EDGE_FLAG_CLAUSE2_ONLY if clause2_only else 0) |
+            (EDGE_FLAG_INVERT_OUT if invert else 0) | (EDGE_FLAG_PLANNED if planned else 0))
 
 
 def _cfg_ptr(cfg):
@@ -100,11 +101,31 @@ def table_to_device(table: np.ndarray, device="cuda") -> torch.Tensor:
     return torch.from_numpy(t.view(np.int64).reshape(-1, 3).copy()).to(device)
 
 
+def plan_batch(in_arena: torch.Tensor, out_arena: torch.Tensor, table: np.ndarray, *,
+               mode: str = "masks", cfg=None, out: np.ndarray | None = None):
+    """Host-side work plan for `table` (host descriptors of the device table)
+    and these device arenas. Returns (plan words, used bytes): copy the first
+    `used bytes` into the workspace and launch with planned=True."""
+    wb = _word_bits(in_arena)
+    t = np.ascontiguousarray(table, dtype=DESC_DTYPE)
+    cfg = _resolve(cfg, len(t), in_arena.numel(), wb, mode)
+    nbytes = batch_workspace_bytes(len(t))
+    if out is None:
+        out = np.zeros(-(-nbytes // 8), dtype=np.int64)
+    used = ctypes.c_int64()
+    check(_lib.edge_batch_plan(in_arena.data_ptr(), out_arena.data_ptr(), in_arena.numel(),
+                               t.ctypes.data if len(t) else None, len(t), wb, _cfg_ptr(cfg),
+                               out.ctypes.data, out.nbytes, ctypes.byref(used)))
+    return out, int(used.value)
+
+
 def edge_batch(in_arena: torch.Tensor, out_arena: torch.Tensor, table_dev: torch.Tensor,
                n_images: int, workspace: torch.Tensor, *, border: str = "white",
                mode: str = "masks", clause2_only: bool = False, invert: bool = False, cfg=None,
-               stream=None) -> None:
-    """Enqueue one batched launch (planner + persistent kernel)."""
+               planned: bool = False, stream=None) -> None:
+    """Enqueue one batched launch: the device planner then the persistent
+    kernel, or (planned=True) the kernel alone on a plan already in the
+    workspace (see plan_batch)."""
     from . import stream_handle
     wb = _word_bits(in_arena)
     if out_arena.dtype != in_arena.dtype or out_arena.numel() != in_arena.numel():
@@ -112,7 +133,8 @@ def edge_batch(in_arena: torch.Tensor, out_arena: torch.Tensor, table_dev: torch
     cfg = _resolve(cfg, n_images, in_arena.numel(), wb, mode)
     check(_lib.edge_batch(in_arena.data_ptr(), out_arena.data_ptr(), in_arena.numel(),
                           table_dev.data_ptr(), n_images, wb, _BORDERS[border], _MODES[mode],
-                          _flags(clause2_only, invert), _cfg_ptr(cfg), workspace.data_ptr(),
+                          _flags(clause2_only, invert, planned), _cfg_ptr(cfg),
+                          workspace.data_ptr(),
                           workspace.numel() * workspace.element_size(), stream_handle(stream)))
 
 
@@ -125,14 +147,15 @@ class BatchGraph:
     """
 
     def __init__(self, in_arena, out_arena, table_dev, n_images, workspace, *,
-                 border="white", mode="masks", clause2_only=False, invert=False, cfg=None):
+                 border="white", mode="masks", clause2_only=False, invert=False, cfg=None,
+                 planned=False):
         wb = _word_bits(in_arena)
         cfg = _resolve(cfg, n_images, in_arena.numel(), wb, mode)
         self._keep = (in_arena, out_arena, table_dev, workspace)
         h = ctypes.c_void_p()
         check(_lib.edge_batch_graph_create(
             in_arena.data_ptr(), out_arena.data_ptr(), in_arena.numel(), table_dev.data_ptr(),
-            n_images, wb, _BORDERS[border], _MODES[mode], _flags(clause2_only, invert),
+            n_images, wb, _BORDERS[border], _MODES[mode], _flags(clause2_only, invert, planned),
             _cfg_ptr(cfg), workspace.data_ptr(), workspace.numel() * workspace.element_size(),
             ctypes.byref(h)))
         self._h = h
@@ -159,23 +182,33 @@ class Batch:
     """Packed images resident in device arenas, ready to launch.
 
     ``images``: sequence of ``(words, width)`` (see pack_arena).
+    ``plan``: "host" (default) plans once on the host and launches the
+    persistent kernel alone; "device" runs the device planner on every
+    launch (needed when the device table is rewritten between launches).
     """
 
     def __init__(self, images, word_bits: int, device="cuda", *, border="white",
-                 mode="masks", clause2_only=False, invert=False, cfg=None, align_words=None):
+                 mode="masks", clause2_only=False, invert=False, cfg=None, align_words=None,
+                 plan: str = "host"):
+        if plan not in ("host", "device"):
+            raise ValueError("plan must be 'host' or 'device'")
         arena, table = pack_arena(images, word_bits, align_words)
         check_table(table, arena.size, word_bits)
         self.word_bits = word_bits
         self.table = table
         self.n = len(table)
-        self.kw = dict(border=border, mode=mode, clause2_only=clause2_only, invert=invert,
-                       cfg=cfg)
         host = torch.from_numpy(arena.view(np.int64 if word_bits == 64 else np.int32))
         self.inp = host.to(device)
         self.out = torch.zeros_like(self.inp)
         self.table_dev = table_to_device(table, device)
         nb = batch_workspace_bytes(self.n)
         self.workspace = torch.zeros(-(-nb // 8), dtype=torch.int64, device=device)
+        cfg = _resolve(cfg, self.n, self.inp.numel(), word_bits, mode)
+        self.kw = dict(border=border, mode=mode, clause2_only=clause2_only, invert=invert,
+                       cfg=cfg, planned=plan == "host")
+        if plan == "host":
+            words, used = plan_batch(self.inp, self.out, table, mode=mode, cfg=cfg)
+            self.workspace[:-(-used // 8)].copy_(torch.from_numpy(words[:-(-used // 8)]))
         self._graph = None
 
     def run(self, stream=None) -> None:

@@ -66,11 +66,14 @@ __host__ __device__ static inline bool desc_ok(const edge_image_desc& d, int64_t
     return d.offset_words <= arena_words - span;
 }
 
-// Workspace layout: int64 words [0] total units, [1] skipped descriptors,
-// [2..7] reserved, [8 + i] first unit of image i (i = 0..n; [8 + n] = total);
-// then, 8-byte aligned, int32 first_image[b] for every persistent workgroup
-// b < kMaxBatchBlocks: the image holding that workgroup's first unit.
+// Work plan (the batch workspace): int64 words [0] total units, [1] skipped
+// descriptors, [2] kPlanMagic ^ n, [3] persistent workgroups the plan was
+// made for, [4..7] reserved, [8 + i] first unit of image i (i = 0..n;
+// [8 + n] = total); then int32 first_image[b] for each persistent workgroup
+// b: the image holding that workgroup's first unit. The device planner or
+// the host planner (edge_batch_plan) writes it.
 constexpr int kWsHeader = 8;
+constexpr int64_t kPlanMagic = 0x45444745504c414ell;   // "EDGEPLAN"
 constexpr int kMaxBatchBlocks = 65536;
 constexpr int kPlanThreads = 1024;
 
@@ -113,6 +116,8 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan(const edge_image_desc* ta
         if (tid == 0) {
             ws[0] = 0;
             ws[1] = 0;
+            ws[2] = kPlanMagic;
+            ws[3] = nblocks;
             start[0] = 0;
         }
         return;
@@ -193,15 +198,24 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan(const edge_image_desc* ta
         start[n] = total;
         ws[0] = total;
         ws[1] = bad_count;     // every atomicAdd precedes the scan's barrier
+        ws[2] = kPlanMagic ^ n;
+        ws[3] = nblocks;
     }
 }
 
 // Persistent batch kernel: wavefront gw of nw processes the contiguous unit
 // range [total*gw/nw, total*(gw+1)/nw) across the images of the table; its
 // first image comes from its workgroup's entry of the planner's map.
+//
+// The plan is checked before use (magic, image count, workgroup count,
+// total = last prefix), and every unit is re-checked against its image
+// (descriptor inside the arena, unit index inside the image), so a plan
+// that does not belong to this table yields wrong output, never an access
+// outside the arenas.
 template <int MODE>
 __global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out,
-                                               const edge_image_desc* tab, int n, int word_bits,
+                                               const edge_image_desc* tab, int n,
+                                               int64_t arena_words, int word_bits,
                                                const int64_t* ws, int vmax, int rows, uint32_t bw,
                                                int invert) {
     const int wpb = blockDim.x / kWave;
@@ -210,14 +224,19 @@ __global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out
     const int64_t gw = (int64_t)lb * wpb + wave_uniform(threadIdx.x / kWave);
     const int64_t total = ws[0];
     const int64_t* start = ws + kWsHeader;
+    if (n <= 0 || ws[2] != (kPlanMagic ^ n) || ws[3] != (int64_t)gridDim.x || total < 0 ||
+        start[n] != total)
+        return;
     const int64_t u0 = total * gw / nw;
     const int64_t u1 = total * (gw + 1) / nw;
     if (u0 >= u1) return;
     int i = reinterpret_cast<const int32_t*>(ws + ws_block_map_offset(n))[lb];
+    i = i < 0 ? 0 : (i >= n ? n - 1 : i);
     const int per = word_bits / 32;
     for (int64_t u = u0; u < u1; ++u) {
-        while (start[i + 1] <= u) ++i;
+        while (i + 1 < n && start[i + 1] <= u) ++i;
         const edge_image_desc d = tab[i];
+        if (!desc_ok(d, arena_words, word_bits) || d.height == 0 || d.width == 0) continue;
         const int64_t wd = ((int64_t)d.width + word_bits - 1) / word_bits * per;
         Geom g;
         g.in = in + d.offset_words * per;
@@ -229,6 +248,7 @@ __global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out
         const UnitShape s = unit_shape(d.height, d.width, wd, d.offset_words * per,
                                        d.stride_words * per, vmax, rows);
         const int64_t local = u - start[i];
+        if (local < 0 || local >= s.count) continue;
         const int64_t strip = local / s.chunks;
         const int64_t chunk = local - strip * s.chunks;
         const int64_t y0 = strip * s.band;
@@ -315,11 +335,13 @@ int64_t pow2_floor(int64_t v) {
     return p;
 }
 
-int common_checks(int word_bits, int border, int mode, uint32_t flags) {
+int common_checks(int word_bits, int border, int mode, uint32_t flags, bool batch = false) {
     if (word_bits != 32 && word_bits != 64) return EDGE_ERR_INVALID;
     if (border != EDGE_BORDER_WHITE && border != EDGE_BORDER_BLACK) return EDGE_ERR_INVALID;
     if (mode != EDGE_MODE_MASKS && mode != EDGE_MODE_FULL) return EDGE_ERR_INVALID;
-    if (flags & ~(uint32_t)(EDGE_FLAG_CLAUSE2_ONLY | EDGE_FLAG_INVERT_OUT)) return EDGE_ERR_INVALID;
+    const uint32_t known = EDGE_FLAG_CLAUSE2_ONLY | EDGE_FLAG_INVERT_OUT |
+                           (batch ? (uint32_t)EDGE_FLAG_PLANNED : 0u);
+    if (flags & ~known) return EDGE_ERR_INVALID;
     if ((flags & EDGE_FLAG_CLAUSE2_ONLY) && mode != EDGE_MODE_FULL) return EDGE_ERR_INVALID;
     return EDGE_OK;
 }
@@ -483,7 +505,7 @@ int batch_validate(const void* in_arena, void* out_arena, int64_t arena_words,
                    const edge_image_desc* table_dev, int32_t n_images, int word_bits, int border,
                    int mode, uint32_t flags, const edge_launch_cfg* cfg, void* workspace_dev,
                    int64_t workspace_bytes, BatchArgs* a) {
-    int rc = common_checks(word_bits, border, mode, flags);
+    int rc = common_checks(word_bits, border, mode, flags, true);
     if (rc) return rc;
     if (n_images < 0 || arena_words < 0) return EDGE_ERR_INVALID;
     if (cfg && !cfg_ok(*cfg)) return EDGE_ERR_INVALID;
@@ -518,23 +540,36 @@ int launch_batch_kernel(const BatchArgs& a, int vmax, int blocks, hipStream_t s)
     const uint32_t bw = border_word(a.border);
     const int inv = (a.flags & EDGE_FLAG_INVERT_OUT) ? 1 : 0;
     hipLaunchKernelGGL(k_batch<MODE>, dim3(blocks), dim3(a.cfg.waves_per_block * kWave), 0, s,
-                       (const uint32_t*)a.in, (uint32_t*)a.out, a.table, a.n, a.word_bits,
-                       (const int64_t*)a.ws, vmax, a.cfg.rows_per_tile, bw, inv);
+                       (const uint32_t*)a.in, (uint32_t*)a.out, a.table, a.n, a.arena_words,
+                       a.word_bits, (const int64_t*)a.ws, vmax, a.cfg.rows_per_tile, bw, inv);
     return launch_status();
 }
 
-int batch_enqueue(const BatchArgs& a, hipStream_t s) {
+// Vector width limit and persistent grid of a batch (same on host and device plans).
+int batch_shape(const void* in, const void* out, const edge_launch_cfg& cfg, int* vmax,
+                int* blocks) {
     int cus = 0;
-    int rc = cu_count(&cus);
+    const int rc = cu_count(&cus);
     if (rc) return rc;
-    int vmax = a.cfg.vec_words;
-    vmax = std::min(vmax, alignment_words((uintptr_t)a.in));
-    vmax = std::min(vmax, alignment_words((uintptr_t)a.out));
-    const int blocks = std::min(a.cfg.blocks_per_cu * cus, kMaxBatchBlocks);
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, a.table, a.n, a.arena_words,
-                       a.word_bits, vmax, a.cfg.rows_per_tile, blocks, (int64_t*)a.ws);
-    rc = launch_status();
+    int v = cfg.vec_words;
+    v = std::min(v, alignment_words((uintptr_t)in));
+    v = std::min(v, alignment_words((uintptr_t)out));
+    *vmax = v;
+    *blocks = std::min(cfg.blocks_per_cu * cus, kMaxBatchBlocks);
+    return EDGE_OK;
+}
+
+int batch_enqueue(const BatchArgs& a, hipStream_t s) {
+    int vmax = 1, blocks = 1;
+    int rc = batch_shape(a.in, a.out, a.cfg, &vmax, &blocks);
     if (rc) return rc;
+    if (!(a.flags & EDGE_FLAG_PLANNED)) {
+        hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, a.table, a.n,
+                           a.arena_words, a.word_bits, vmax, a.cfg.rows_per_tile, blocks,
+                           (int64_t*)a.ws);
+        rc = launch_status();
+        if (rc) return rc;
+    }
     switch (kernel_mode(a.mode, a.flags)) {
         case kModePlain: return launch_batch_kernel<kModePlain>(a, vmax, blocks, s);
         case kModeFull: return launch_batch_kernel<kModeFull>(a, vmax, blocks, s);
@@ -610,6 +645,54 @@ int edge_batch_check(const edge_image_desc* table_host, int32_t n_images, int64_
     if (n_images > 0 && !table_host) return EDGE_ERR_INVALID;
     for (int32_t i = 0; i < n_images; ++i)
         if (!desc_ok(table_host[i], arena_words, word_bits)) return EDGE_ERR_INVALID;
+    return EDGE_OK;
+}
+
+int edge_batch_plan(const void* in_arena, const void* out_arena, int64_t arena_words,
+                    const edge_image_desc* table_host, int32_t n_images, int word_bits,
+                    const edge_launch_cfg* cfg, void* plan_host, int64_t plan_bytes,
+                    int64_t* plan_used_bytes) {
+    if (n_images < 0 || arena_words < 0 || !plan_used_bytes) return EDGE_ERR_INVALID;
+    if (word_bits != 32 && word_bits != 64) return EDGE_ERR_INVALID;
+    if (cfg && !cfg_ok(*cfg)) return EDGE_ERR_INVALID;
+    if (!in_arena || !out_arena || (n_images > 0 && !table_host)) return EDGE_ERR_INVALID;
+    if (!plan_host || plan_bytes < edge_batch_workspace_bytes(n_images) ||
+        (uintptr_t)plan_host % 8)
+        return EDGE_ERR_WORKSPACE;
+    int rc = edge_batch_check(table_host, n_images, arena_words, word_bits);
+    if (rc) return rc;
+    const edge_launch_cfg c = cfg ? *cfg : default_batch();
+    int vmax = 1, blocks = 1;
+    rc = batch_shape(in_arena, out_arena, c, &vmax, &blocks);
+    if (rc) return rc;
+    int64_t* ws = (int64_t*)plan_host;
+    int64_t* start = ws + kWsHeader;
+    int32_t* block_image = (int32_t*)(ws + ws_block_map_offset(n_images));
+    const int per = word_bits / 32;
+    int64_t total = 0;
+    for (int32_t i = 0; i < n_images; ++i) {
+        const edge_image_desc& d = table_host[i];
+        start[i] = total;
+        const int64_t wd = ((int64_t)d.width + word_bits - 1) / word_bits * per;
+        total += unit_shape(d.height, d.width, wd, d.offset_words * per, d.stride_words * per,
+                            vmax, c.rows_per_tile).count;
+    }
+    start[n_images] = total;
+    for (int k = 0; k < kWsHeader; ++k) ws[k] = 0;
+    ws[0] = total;
+    ws[2] = kPlanMagic ^ n_images;
+    ws[3] = blocks;
+    int32_t i = 0;
+    for (int b = 0; b < blocks; ++b) {
+        if (total == 0) {
+            block_image[b] = 0;
+            continue;
+        }
+        const int64_t ub = total * b / blocks;
+        while (i + 1 < n_images && start[i + 1] <= ub) ++i;
+        block_image[b] = i;
+    }
+    *plan_used_bytes = (ws_block_map_offset(n_images) * 8) + (int64_t)blocks * 4;
     return EDGE_OK;
 }
 

@@ -192,6 +192,7 @@ class Server:
             self.slots.append({
                 "table_host": torch.zeros(max_batch * 3, dtype=torch.int64).pin_memory(),
                 "table_dev": torch.zeros(max_batch * 3, dtype=torch.int64, device=device),
+                "plan_host": torch.zeros(-(-nb // 8), dtype=torch.int64).pin_memory(),
                 "ws": torch.zeros(-(-nb // 8), dtype=torch.int64, device=device),
                 "busy": False})
         self._tab = np.zeros(max_batch, dtype=_batch.DESC_DTYPE)
@@ -314,9 +315,15 @@ class Server:
                             tab["stride_words"] = table["stride_words"][pidx]
                             th = S["table_host"]
                             th[:k * 3].numpy()[:] = tab.view(np.int64)
+                            ph = S["plan_host"]
+                            _, used = _batch.plan_batch(dev_in, dev_out, tab,
+                                                        mode=self.kw["mode"],
+                                                        cfg=self.kw["cfg"], out=ph.numpy())
+                            nw = -(-used // 8)
                             S["table_dev"][:k * 3].copy_(th[:k * 3], non_blocking=True)
+                            S["ws"][:nw].copy_(ph[:nw], non_blocking=True)
                             _batch.edge_batch(dev_in, dev_out, S["table_dev"], k, S["ws"],
-                                              stream=self.s_k, **self.kw)
+                                              planned=True, stream=self.s_k, **self.kw)
                         ev_k = torch.cuda.Event()
                         ev_k.record(self.s_k)
                     self.s_out.wait_event(ev_k)

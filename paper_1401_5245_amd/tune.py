@@ -188,28 +188,41 @@ def tune_batch(batch, *, candidates=None, cache: TuneCache | None = None, launch
                verbose=False):
     """Tune the persistent batch launch of a Batch (its table and arenas).
     Returns (cfg, microseconds per batched launch)."""
-    from .batch import edge_batch
+    from .batch import edge_batch, plan_batch
     kw = dict(batch.kw)
     kw.pop("cfg", None)
+    kw.pop("planned", None)
     edge_batch(batch.inp, batch.out, batch.table_dev, batch.n, batch.workspace, **kw)
     torch.cuda.synchronize()
     ref = batch.out.clone()
     best, best_us, tried = None, float("inf"), 0
+    ws = batch.workspace
     for c in (list(candidates) if candidates is not None else list(batch_candidates())):
+        # each candidate gets its own host plan; the timed launches are the
+        # persistent kernel alone, as Batch runs them
+        words, used = plan_batch(batch.inp, batch.out, batch.table, mode=kw.get("mode", "masks"),
+                                 cfg=c)
+        ws[:-(-used // 8)].copy_(torch.from_numpy(words[:-(-used // 8)]))
+        kw["planned"] = True
         batch.out.zero_()
-        edge_batch(batch.inp, batch.out, batch.table_dev, batch.n, batch.workspace, cfg=c, **kw)
+        edge_batch(batch.inp, batch.out, batch.table_dev, batch.n, ws, cfg=c, **kw)
         torch.cuda.synchronize()
         if not torch.equal(batch.out, ref):
             if verbose:
                 print("rejected (output differs):", c)
             continue
         us = _graph_time_us(lambda: edge_batch(batch.inp, batch.out, batch.table_dev, batch.n,
-                                               batch.workspace, cfg=c, **kw), launches, reps)
+                                               ws, cfg=c, **kw), launches, reps)
         tried += 1
         if verbose:
             print(f"{us:9.2f} us  {c}")
         if us < best_us:
             best, best_us = c, us
+    # leave the batch's own plan in its workspace again
+    if batch.kw.get("planned"):
+        words, used = plan_batch(batch.inp, batch.out, batch.table, mode=kw.get("mode", "masks"),
+                                 cfg=batch.kw.get("cfg"))
+        ws[:-(-used // 8)].copy_(torch.from_numpy(words[:-(-used // 8)]))
     if best is None:
         raise RuntimeError("no candidate configuration matched the built-in output")
     if cache is not None:

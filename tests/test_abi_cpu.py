@@ -147,3 +147,21 @@ def test_copy_validation():
     assert lib.edge_copy_bytes(A + 8, B, 16, None) == ALIGN
     assert lib.edge_copy_bytes(A, A + 16, 64, None) == ALIAS
     assert lib.edge_copy_bytes(A, B, 0, None) == OK
+
+
+def test_planned_flag_and_host_plan_validation():
+    planned = _abi.EDGE_FLAG_PLANNED
+    assert launch(flags=planned) == INVALID          # single-image calls reject it
+    used = ctypes.c_int64()
+    P = 0x40000000
+    big = 1 << 20
+    assert lib.edge_batch_plan(A, B, 100, None, 1, 32, None, P, big, ctypes.byref(used)) == INVALID
+    assert lib.edge_batch_plan(A, B, 100, None, 0, 48, None, P, big, ctypes.byref(used)) == INVALID
+    assert lib.edge_batch_plan(A, B, 100, None, 0, 32, None, P, 8, ctypes.byref(used)) == WS
+    assert lib.edge_batch_plan(A, B, 100, None, 0, 32, None, P + 4, big, ctypes.byref(used)) == WS
+    assert lib.edge_batch_plan(A, B, -1, None, 0, 32, None, P, big, ctypes.byref(used)) == INVALID
+    assert lib.edge_batch_plan(A, B, 100, None, 0, 32, None, P, big, None) == INVALID
+    bad = table([(0, 2, 40, 1)])                      # stride below the row's words
+    buf = np.zeros(lib.edge_batch_workspace_bytes(1) // 8, np.int64)
+    assert lib.edge_batch_plan(A, B, 100, bad.ctypes.data, 1, 32, None, buf.ctypes.data,
+                               buf.nbytes, ctypes.byref(used)) == INVALID

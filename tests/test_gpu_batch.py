@@ -25,11 +25,11 @@ def mixed_images(n, seed, side=(1, 700)):
 
 
 def run_batch(imgs, word_bits, *, border="white", mode="masks", clause2_only=False,
-              invert=False, cfg=None, pad="random", align_words=None):
+              invert=False, cfg=None, pad="random", align_words=None, plan="host"):
     import paper_1401_5245_amd as em
     packed = [(pack_rows(im, word_bits, pad=pad, seed=i), im.shape[1]) for i, im in enumerate(imgs)]
     b = em.Batch(packed, word_bits, "cuda", border=border, mode=mode, clause2_only=clause2_only,
-                 invert=invert, cfg=cfg, align_words=align_words)
+                 invert=invert, cfg=cfg, align_words=align_words, plan=plan)
     b.run()
     torch.cuda.synchronize()
     return b
@@ -51,10 +51,12 @@ def check_batch(b, imgs, **kw):
 @pytest.mark.parametrize("mode,c2,inv", [("masks", False, False), ("full", False, False),
                                          ("full", True, False), ("masks", False, True)])
 @pytest.mark.parametrize("border", ["white", "black"])
-def test_mixed_batch_matches_oracle(word_bits, mode, c2, inv, border):
+@pytest.mark.parametrize("plan", ["host", "device"])
+def test_mixed_batch_matches_oracle(word_bits, mode, c2, inv, border, plan):
     imgs = mixed_images(60, seed=word_bits + len(mode) + int(c2) + int(inv))
-    log(f"batch B={word_bits} {mode} c2={c2} inv={inv} {border}")
-    b = run_batch(imgs, word_bits, border=border, mode=mode, clause2_only=c2, invert=inv)
+    log(f"batch B={word_bits} {mode} c2={c2} inv={inv} {border} plan={plan}")
+    b = run_batch(imgs, word_bits, border=border, mode=mode, clause2_only=c2, invert=inv,
+                  plan=plan)
     check_batch(b, imgs, border=border, mode=mode, clause2_only=c2, invert=inv)
 
 
@@ -79,8 +81,27 @@ def test_batch_launch_configs(vec, rows, waves, bpc):
     imgs = mixed_images(25, seed=5, side=(1, 1500))
     cfg = dict(vec_words=vec, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=bpc,
                cache_policy=1)
-    b = run_batch(imgs, 64, cfg=cfg, mode="full", clause2_only=(rows % 2 == 1))
+    b = run_batch(imgs, 64, cfg=cfg, mode="full", clause2_only=(rows % 2 == 1),
+                  plan="host" if (vec + rows + waves + bpc) % 2 else "device")
     check_batch(b, imgs, mode="full", clause2_only=(rows % 2 == 1))
+
+
+def test_host_plan_graph_replays():
+    """A host-planned batch captured in a graph: replays (with eager work in
+    between) equal the eager launch, which equals the device-planned one."""
+    imgs = mixed_images(50, seed=17, side=(1, 900))
+    b = run_batch(imgs, 64, plan="host")
+    d = run_batch(imgs, 64, plan="device")
+    assert torch.equal(b.out, d.out)
+    eager = b.out.clone()
+    g = b.graph()
+    for rep in range(4):
+        b.out.zero_()
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(b.out, eager), f"replay {rep}"
+    check_batch(b, imgs)
 
 
 def test_batch_equals_single_image_path():
@@ -107,7 +128,7 @@ def test_graph_replays_with_eager_work_between():
     import paper_1401_5245_amd as em
     from paper_1401_5245_amd.batch import DESC_DTYPE
     imgs = mixed_images(40, seed=11, side=(10, 600))
-    b = run_batch(imgs, 64)
+    b = run_batch(imgs, 64, plan="device")     # the table is rewritten on the device below
     eager = b.out.clone()
     g = b.graph()
     junk = torch.randn(1 << 20, device="cuda")
