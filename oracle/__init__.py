@@ -55,6 +55,12 @@ def _load():
     lib.oracle_edge_image.restype = ctypes.c_int
     lib.oracle_edge_stack.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64] + argt[2:]
     lib.oracle_edge_stack.restype = ctypes.c_int
+    lib.oracle_fundamental_edges.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                             ctypes.c_int64, ctypes.c_int]
+    lib.oracle_fundamental_edges.restype = ctypes.c_int
+    lib.oracle_threshold.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_int64, ctypes.c_int]
+    lib.oracle_threshold.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -98,6 +104,37 @@ def edge_stack(imgs: np.ndarray, border: str = "white", clauses: int = CLAUSE1,
                                    _BORDER_PIXEL[border], int(clauses), int(bool(invert)))
     if rc != 0:
         raise ValueError(f"oracle_edge_stack rejected its arguments ({rc})")
+    return out
+
+
+DIRECTIONS = ("left", "right", "up", "down")
+
+
+def fundamental_edges(img: np.ndarray, border: str = "white") -> np.ndarray:
+    """The four fundamental edges of section 4 of an (H, W) byte image:
+    a (4, H, W) uint8 array, planes ordered left, right, up, down."""
+    a = _as_bytes(img)
+    if a.ndim != 2:
+        raise ValueError("expected a 2-D image")
+    H, W = a.shape
+    out = np.empty((4, H, W), dtype=np.uint8)
+    rc = _load().oracle_fundamental_edges(a.ctypes.data, out.ctypes.data, H, W,
+                                          _BORDER_PIXEL[border])
+    if rc != 0:
+        raise ValueError(f"oracle_fundamental_edges rejected its arguments ({rc})")
+    return out
+
+
+def threshold(grey: np.ndarray, t: int) -> np.ndarray:
+    """Binary image of a uint8 grey image: 1 (white) where grey >= t."""
+    g = np.ascontiguousarray(grey, dtype=np.uint8)
+    if g.ndim != 2:
+        raise ValueError("expected a 2-D image")
+    H, W = g.shape
+    out = np.empty((H, W), dtype=np.uint8)
+    rc = _load().oracle_threshold(g.ctypes.data, out.ctypes.data, H, W, int(t))
+    if rc != 0:
+        raise ValueError(f"oracle_threshold rejected its arguments ({rc})")
     return out
 
 

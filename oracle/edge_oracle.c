@@ -94,6 +94,42 @@ int oracle_edge_image(const uint8_t* img, uint8_t* out, int64_t H, int64_t W,
     return 0;
 }
 
+/* The four fundamental edges of section 4, as four byte planes of H x W
+ * in the order the section names them: left, right, up, down. The left
+ * edge is the image shifted right by one pixel ANDed with the mask (the
+ * negative image, section 3): a black point whose left neighbour (n4 of
+ * Fig. 1) is white. Likewise right uses n8, up uses n2 and down uses n6;
+ * these are the four types of Fig. 2. */
+int oracle_fundamental_edges(const uint8_t* img, uint8_t* out4, int64_t H, int64_t W,
+                             int border_pixel) {
+    static const int DIRECTION_NEIGHBOUR[4] = {4, 8, 2, 6};   /* left, right, up, down */
+    if (H < 0 || W < 0) return -1;
+    if (border_pixel != 0 && border_pixel != 1) return -1;
+    if (H * W > 0 && (img == NULL || out4 == NULL)) return -1;
+    for (int plane = 0; plane < 4; ++plane) {
+        const int k = DIRECTION_NEIGHBOUR[plane];
+        uint8_t* out = out4 + (int64_t)plane * H * W;
+        for (int64_t y = 0; y < H; ++y)
+            for (int64_t x = 0; x < W; ++x) {
+                const int mask = 1 - pixel(img, H, W, y, x, border_pixel);   /* section 3 */
+                const int shifted = pixel(img, H, W, y + DY[k], x + DX[k], border_pixel);
+                out[y * W + x] = (uint8_t)(mask & shifted);
+            }
+    }
+    return 0;
+}
+
+/* Binarisation of a grey image by a threshold (section 7: non-binary images
+ * are first converted to binary by thresholding). A grey value >= threshold
+ * becomes white (1), a smaller one black (0), so dark strokes stay black.
+ * threshold 0 makes every pixel white, 256 every pixel black. */
+int oracle_threshold(const uint8_t* grey, uint8_t* out, int64_t H, int64_t W, int threshold) {
+    if (H < 0 || W < 0 || threshold < 0 || threshold > 256) return -1;
+    if (H * W > 0 && (grey == NULL || out == NULL)) return -1;
+    for (int64_t i = 0; i < H * W; ++i) out[i] = (uint8_t)(grey[i] >= threshold ? 1 : 0);
+    return 0;
+}
+
 /* The same for n images of equal shape stored one after another. */
 int oracle_edge_stack(const uint8_t* imgs, uint8_t* outs, int64_t n, int64_t H,
                       int64_t W, int border_pixel, int clauses, int invert) {

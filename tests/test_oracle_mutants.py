@@ -29,12 +29,23 @@ MUTANTS = {
     "inverted_colour": ("return img[y * W + x] != 0;", "return img[y * W + x] == 0;"),
     "invert_ignored": ("(invert ? !edge : edge)", "(edge)"),
     "clause2_strict": ("if (black_8 <= 1)", "if (black_8 < 1)"),
+    "planes_swapped": ("DIRECTION_NEIGHBOUR[4] = {4, 8, 2, 6}", "DIRECTION_NEIGHBOUR[4] = {8, 4, 2, 6}"),
+    "plane_diagonal": ("DIRECTION_NEIGHBOUR[4] = {4, 8, 2, 6}", "DIRECTION_NEIGHBOUR[4] = {4, 8, 1, 6}"),
+    "plane_no_mask": ("const int mask = 1 - pixel(", "const int mask = 1 | pixel("),
+    "threshold_strict": ("grey[i] >= threshold ? 1 : 0", "grey[i] > threshold ? 1 : 0"),
+    "threshold_inverted": ("grey[i] >= threshold ? 1 : 0", "grey[i] >= threshold ? 0 : 1"),
 }
 
 
 def _pin_suite(golden_dir):
     """The pin tests, run one after another; returns the first failure."""
+    from tests import test_oracle_pins_next as nxt
     checks = [
+        lambda: nxt.test_fig2_names_match_planes(golden_dir),
+        lambda: nxt.test_single_white_neighbour_fires_one_plane(golden_dir),
+        lambda: [nxt.test_planes_match_shifted_ands_and_or_to_edge(s, b)
+                 for s in [(17, 33)] for b in pins.BORDERS],
+        lambda: nxt.test_threshold_by_histogram_and_bounds(),
         lambda: pins.test_fig1_four_neighbours_are_2_4_6_8(golden_dir),
         lambda: pins.test_fig2_patterns_are_edge_points(golden_dir),
         lambda: pins.test_fig2_patterns_cover_every_edge_point(golden_dir),
@@ -65,7 +76,8 @@ def test_mutant_is_caught(name, tmp_path, monkeypatch, golden_dir):
                    check=True)
     lib = ctypes.CDLL(str(so))
     real = oracle._load()
-    for fn in ("oracle_edge_image", "oracle_edge_stack"):
+    for fn in ("oracle_edge_image", "oracle_edge_stack", "oracle_fundamental_edges",
+               "oracle_threshold"):
         getattr(lib, fn).argtypes = getattr(real, fn).argtypes
         getattr(lib, fn).restype = ctypes.c_int
     monkeypatch.setattr(oracle, "_lib", lib)
