@@ -141,6 +141,39 @@ int edge_image_launch(const void* in, void* out, int64_t height, int64_t width,
                       int64_t stride_words, int word_bits, int border, int mode,
                       uint32_t flags, const edge_launch_cfg* cfg, void* hip_stream);
 
+/* The four fundamental edges of section 4 - the edge types of Fig. 2 -
+ * as four planes: out4 + 0, 1, 2, 3 x plane_words hold the left, right, up
+ * and down edges (the mask ANDed with the image shifted right, left, down
+ * and up by one pixel: black pixels whose n4, n8, n2 or n6 neighbour is
+ * white). Their OR is edge_masks's output. Each plane has the input's
+ * layout; plane_words >= (height - 1) * stride_words + ceil(width / B).
+ * cfg: NULL or as for edge_image_launch. */
+int edge_directions(const void* in, void* out4, int64_t plane_words, int64_t height,
+                    int64_t width, int64_t stride_words, int word_bits, int border,
+                    const edge_launch_cfg* cfg, void* hip_stream);
+
+/* Binarisation by a threshold (section 7: a non-binary image is made
+ * binary first) and packing. grey: device bytes, height rows of
+ * grey_stride_bytes (>= width) bytes. A grey value >= threshold becomes white
+ * (1), a smaller one black (0); threshold 0..256 (0: all white, 256: all
+ * black). out: packed rows in the layout above (stride_words words of
+ * word_bits), bits past the width written 0, stride words untouched.
+ * 16-byte aligned grey rows load 128 bits at a time. */
+int edge_threshold_pack(const void* grey, int64_t grey_stride_bytes, int threshold, void* out,
+                        int64_t height, int64_t width, int64_t stride_words, int word_bits,
+                        void* hip_stream);
+
+/* Threshold and edges in one pass: the grey image of edge_threshold_pack
+ * is binarised in registers and its edge map (mode, flags and border as
+ * for edge_image_launch) written in the packed layout; the binary image is
+ * never stored. Equals edge_threshold_pack followed by edge_image_launch.
+ * cfg: NULL or a configuration whose vec_words is ignored (one 32-bit word
+ * of 32 grey bytes per lane). */
+int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int threshold, void* out,
+                         int64_t height, int64_t width, int64_t stride_words, int word_bits,
+                         int border, int mode, uint32_t flags, const edge_launch_cfg* cfg,
+                         void* hip_stream);
+
 /* Built-in launch configuration for an image shape (batch != 0: for the
  * persistent batch kernel). Returns EDGE_OK and fills *cfg_out. */
 int edge_default_cfg(int64_t height, int64_t width, int word_bits, int mode,

@@ -112,6 +112,56 @@ def edge_image(inp: torch.Tensor, out: torch.Tensor, height: int, width: int, *,
     return out
 
 
+def edge_directions(inp: torch.Tensor, out4: torch.Tensor, height: int, width: int, *,
+                    border: str = "white", cfg=None, stride_words=None, stream=None):
+    """The four fundamental edges of section 4 (the edge types of Fig. 2).
+
+    ``out4`` holds four planes of the input's layout, in the order left,
+    right, up, down: a (4, H, stride) tensor, or one whose numel is a
+    multiple of 4 (planes back to back). Their OR equals edge_masks."""
+    wb, s = _image_args(inp, out4.view(4, -1)[0], height, width, stride_words)
+    plane = out4.numel() // 4
+    c = _resolve_cfg(cfg, height, width, wb, "masks")
+    check(_lib.edge_directions(inp.data_ptr(), out4.data_ptr(), plane, height, width, s, wb,
+                               BORDERS[border], _cfg_ptr(c), stream_handle(stream)))
+    return out4
+
+
+def threshold_pack(grey: torch.Tensor, out: torch.Tensor, height: int, width: int,
+                   threshold: int, *, grey_stride=None, stride_words=None, stream=None):
+    """Binarise a uint8 grey image (white where grey >= threshold) into
+    packed rows (section 7's conversion of a non-binary image)."""
+    if grey.dtype != torch.uint8 or not grey.is_cuda or not grey.is_contiguous():
+        raise TypeError("grey must be a contiguous uint8 device tensor")
+    gs = int(grey_stride if grey_stride is not None else grey.shape[-1])
+    if height and width and grey.numel() < (height - 1) * gs + width:
+        raise ValueError("grey tensor smaller than the image")
+    wb, s = _image_args(out, out, height, width, stride_words)
+    check(_lib.edge_threshold_pack(grey.data_ptr(), gs, int(threshold), out.data_ptr(), height,
+                                   width, s, wb, stream_handle(stream)))
+    return out
+
+
+def threshold_edges(grey: torch.Tensor, out: torch.Tensor, height: int, width: int,
+                    threshold: int, *, mode: str = "masks", border: str = "white",
+                    clause2_only: bool = False, invert: bool = False, cfg=None,
+                    grey_stride=None, stride_words=None, stream=None):
+    """Edge map of a uint8 grey image binarised at `threshold`, in one pass
+    (the binary image is never written)."""
+    if grey.dtype != torch.uint8 or not grey.is_cuda or not grey.is_contiguous():
+        raise TypeError("grey must be a contiguous uint8 device tensor")
+    gs = int(grey_stride if grey_stride is not None else grey.shape[-1])
+    if height and width and grey.numel() < (height - 1) * gs + width:
+        raise ValueError("grey tensor smaller than the image")
+    wb, s = _image_args(out, out, height, width, stride_words)
+    flags = (EDGE_FLAG_CLAUSE2_ONLY if clause2_only else 0) | (EDGE_FLAG_INVERT_OUT if invert else 0)
+    c = None if cfg is None else (EdgeLaunchCfg.from_dict(cfg) if isinstance(cfg, dict) else cfg)
+    check(_lib.edge_threshold_edges(grey.data_ptr(), gs, int(threshold), out.data_ptr(), height,
+                                    width, s, wb, BORDERS[border], MODES[mode], flags,
+                                    _cfg_ptr(c), stream_handle(stream)))
+    return out
+
+
 def default_cfg(height: int, width: int, word_bits: int, mode: str = "masks",
                 batch: bool = False) -> dict:
     c = EdgeLaunchCfg()

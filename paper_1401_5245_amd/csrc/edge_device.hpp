@@ -29,13 +29,17 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace edgek {
 
 constexpr int kWave = 64;
 constexpr int kNarrowSteps = 4; // narrow-unit steps loaded ahead of use
 constexpr int kNarrowMaxWords = 32;
 
-enum { kModePlain = 0, kModeFull = 1, kModeClause2 = 2 };
+// kModeDirections writes the four fundamental edges of section 4 (left,
+// right, up, down: the edge types of Fig. 2) to four output planes.
+enum { kModePlain = 0, kModeFull = 1, kModeClause2 = 2, kModeDirections = 3 };
 
 // Compile-time choices of the strip loop: rows kept in flight per lane, and
 // non-temporal (streaming) cache policy for the row loads and stores.
@@ -61,7 +65,28 @@ struct Geom {
     int32_t height;   // rows
     int32_t width;    // pixels per row
     int32_t wd;       // words per row the kernels touch (whole B-bit words)
+    int64_t plane;    // words between output planes (kModeDirections only)
+    // grey input (threshold then edges): rows of grey_stride bytes; a byte
+    // >= thr is white. Used when the strip runs with GREY set.
+    const uint8_t* grey;
+    int64_t grey_stride;
+    uint32_t thr;
 };
+
+// Bits 0..3 of the result: bytes 0..3 of `four` >= thr (white pixels).
+__device__ __forceinline__ uint32_t ge_bits4(uint32_t four, uint32_t thr) {
+    uint32_t bits = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bits |= (((four >> (8 * b)) & 0xffu) >= thr ? 1u : 0u) << b;
+    return bits;
+}
+
+// One packed word from 32 grey bytes held in two 128-bit values.
+__device__ __forceinline__ uint32_t threshold_word(const u32x4& a, const u32x4& b, uint32_t thr) {
+    return ge_bits4(a.x, thr) | ge_bits4(a.y, thr) << 4 | ge_bits4(a.z, thr) << 8 |
+           ge_bits4(a.w, thr) << 12 | ge_bits4(b.x, thr) << 16 | ge_bits4(b.y, thr) << 20 |
+           ge_bits4(b.z, thr) << 24 | ge_bits4(b.w, thr) << 28;
+}
 
 // ------------------------------------------------------------ word helpers --
 
@@ -187,9 +212,17 @@ __device__ __forceinline__ void store_words(uint32_t* p, const uint32_t (&w)[VW]
 // outside the image are clamped into it and replaced by the border after
 // the load, so the hardware's in-order load counter waits exactly for the
 // row being consumed.
-template <int VW, int MODE, bool WHOLE, bool EDGES, class Pol>
+//
+// GREY (one word per lane): the input is a grey image; each lane reads the
+// 32 bytes of its word, thresholds and packs them in registers, so the
+// binary image never exists in memory (section 7's conversion fused into
+// the edge pass). WHOLE then also means every byte of the span lies inside
+// the row and rows are 16-byte aligned; otherwise bytes load one by one
+// from clamped addresses.
+template <int VW, int MODE, bool WHOLE, bool EDGES, class Pol, bool GREY = false>
 __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1, uint32_t bw,
                                            bool invert) {
+    static_assert(!GREY || VW == 1, "grey input runs one word per lane");
     constexpr int P = Pol::prefetch;
     const int lane = threadIdx.x & (kWave - 1);
     const int jl = j0 + lane * VW;
@@ -212,21 +245,49 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
     const int je_load = has_e ? je : j0;
     const uint32_t vme = valid_bits(je, g.width), ome = bw & ~vme;
 
-    struct Raw { uint32_t w[VW]; uint32_t e; };
+    struct RawPacked { uint32_t w[VW]; uint32_t e; };
+    struct RawGrey { u32x4 b[2]; uint32_t e; };
+    using Raw = std::conditional_t<GREY, RawGrey, RawPacked>;
     struct Row { uint32_t c[VW], w[VW], e[VW]; };
+    // grey input: the neighbour pixel just outside the span (its byte)
+    const int64_t xe_load = lane == 0 ? 32ll * j0 - 1 : 32ll * (j0 + kWave);
 
     auto load_raw = [&](int y) {
         const int yc = y < 0 ? 0 : (y >= g.height ? g.height - 1 : y);
-        const uint32_t* rp = g.in + (int64_t)yc * g.stride;
         Raw r;
-        if constexpr (WHOLE) {
-            load_words<VW, Pol::nt_load>(rp + jl, r.w);
-        } else {
+        if constexpr (GREY) {
+            const uint8_t* rp = g.grey + (int64_t)yc * g.grey_stride;
+            if constexpr (WHOLE) {
+                const u32x4* vp = reinterpret_cast<const u32x4*>(rp + 32ll * jl);
+                r.b[0] = Pol::nt_load ? __builtin_nontemporal_load(vp) : vp[0];
+                r.b[1] = Pol::nt_load ? __builtin_nontemporal_load(vp + 1) : vp[1];
+            } else {
+                uint32_t d[8];
 #pragma unroll
-            for (int k = 0; k < VW; ++k) r.w[k] = rp[jw[k]];
+                for (int q = 0; q < 8; ++q) {
+                    d[q] = 0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int64_t x = 32ll * jl + 4 * q + b;
+                        d[q] |= (uint32_t)rp[x < g.width ? x : g.width - 1] << (8 * b);
+                    }
+                }
+                r.b[0].x = d[0]; r.b[0].y = d[1]; r.b[0].z = d[2]; r.b[0].w = d[3];
+                r.b[1].x = d[4]; r.b[1].y = d[5]; r.b[1].z = d[6]; r.b[1].w = d[7];
+            }
+            if constexpr (EDGES) r.e = rp[has_e ? xe_load : 0];
+            else r.e = 0;
+        } else {
+            const uint32_t* rp = g.in + (int64_t)yc * g.stride;
+            if constexpr (WHOLE) {
+                load_words<VW, Pol::nt_load>(rp + jl, r.w);
+            } else {
+#pragma unroll
+                for (int k = 0; k < VW; ++k) r.w[k] = rp[jw[k]];
+            }
+            if constexpr (EDGES) r.e = rp[je_load];
+            else r.e = bw;
         }
-        if constexpr (EDGES) r.e = rp[je_load];
-        else r.e = bw;
         return r;
     };
 
@@ -237,9 +298,16 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
     auto shift_row = [&](const Raw& r, int y) {
         const bool inside = (unsigned)y < (unsigned)g.height;
         Row o;
+        uint32_t e;
+        if constexpr (GREY) {
+            o.c[0] = inside ? ((threshold_word(r.b[0], r.b[1], g.thr) & vm[0]) | om[0]) : bw;
+            // only the neighbour pixel's bit is used by the carries
+            e = (EDGES && inside && has_e) ? (r.e >= g.thr ? 0xffffffffu : 0u) : bw;
+        } else {
 #pragma unroll
-        for (int k = 0; k < VW; ++k) o.c[k] = inside ? ((r.w[k] & vm[k]) | om[k]) : bw;
-        const uint32_t e = (EDGES && inside && has_e) ? ((r.e & vme) | ome) : bw;
+            for (int k = 0; k < VW; ++k) o.c[k] = inside ? ((r.w[k] & vm[k]) | om[k]) : bw;
+            e = (EDGES && inside && has_e) ? ((r.e & vme) | ome) : bw;
+        }
         const uint32_t left = from_lower_lane(o.c[VW - 1], e);
         const uint32_t right = from_upper_lane(o.c[0], e);
 #pragma unroll
@@ -250,21 +318,44 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
         return o;
     };
 
-    auto emit = [&](int y, const Row& up, const Row& cur, const Row& dn) {
-        uint32_t res[VW];
-#pragma unroll
-        for (int k = 0; k < VW; ++k) {
-            const uint32_t v = edge_word<MODE>(cur.c[k], up.e[k], up.c[k], up.w[k], cur.w[k],
-                                               dn.w[k], dn.c[k], dn.e[k], cur.e[k]) & vm[k];
-            res[k] = invert ? (v ^ vm[k]) : v;
-        }
-        uint32_t* op = g.out + (int64_t)y * g.stride;
+    auto store_row = [&](uint32_t* op, const uint32_t (&res)[VW]) {
         if constexpr (WHOLE) {
             store_words<VW, Pol::nt_store>(op + jl, res);
         } else {
 #pragma unroll
             for (int k = 0; k < VW; ++k)
                 if (inrow[k]) op[jl + k] = res[k];
+        }
+    };
+
+    auto emit = [&](int y, const Row& up, const Row& cur, const Row& dn) {
+        uint32_t* op = g.out + (int64_t)y * g.stride;
+        if constexpr (MODE == kModeDirections) {
+            // fundamental edges (section 4): the mask ANDed with the image
+            // shifted right (left edge, n4), left (right edge, n8), down
+            // (up edge, n2) and up (down edge, n6)
+            uint32_t l[VW], r[VW], u[VW], d[VW];
+#pragma unroll
+            for (int k = 0; k < VW; ++k) {
+                const uint32_t m = ~cur.c[k] & vm[k];
+                l[k] = m & cur.w[k];
+                r[k] = m & cur.e[k];
+                u[k] = m & up.c[k];
+                d[k] = m & dn.c[k];
+            }
+            store_row(op, l);
+            store_row(op + g.plane, r);
+            store_row(op + 2 * g.plane, u);
+            store_row(op + 3 * g.plane, d);
+        } else {
+            uint32_t res[VW];
+#pragma unroll
+            for (int k = 0; k < VW; ++k) {
+                const uint32_t v = edge_word<MODE>(cur.c[k], up.e[k], up.c[k], up.w[k], cur.w[k],
+                                                   dn.w[k], dn.c[k], dn.e[k], cur.e[k]) & vm[k];
+                res[k] = invert ? (v ^ vm[k]) : v;
+            }
+            store_row(op, res);
         }
     };
 
@@ -300,6 +391,22 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
             up = cur;
             cur = dn;
         }
+    }
+}
+
+// Grey input (threshold then edges), one word per lane. vec: the grey
+// pointer and pitch are 16-byte aligned.
+template <int MODE, class Pol>
+__device__ __forceinline__ void grey_strip_unit(const Geom& g, int j0, int y0, int y1,
+                                                uint32_t bw, bool invert, bool vec) {
+    const bool whole = vec && (int64_t)(j0 + kWave) * 32 <= g.width;
+    const bool edges = j0 > 0 || j0 + kWave < g.wd;
+    if (whole) {
+        if (edges) strip_body<1, MODE, true, true, Pol, true>(g, j0, y0, y1, bw, invert);
+        else strip_body<1, MODE, true, false, Pol, true>(g, j0, y0, y1, bw, invert);
+    } else {
+        if (edges) strip_body<1, MODE, false, true, Pol, true>(g, j0, y0, y1, bw, invert);
+        else strip_body<1, MODE, false, false, Pol, true>(g, j0, y0, y1, bw, invert);
     }
 }
 
@@ -358,16 +465,27 @@ __device__ __forceinline__ void narrow_unit(const Geom& g, int ya, int yb, uint3
             if (j == 0) cl = bw;
             if (j == wd - 1) cr = bw;
             uint32_t ul = bw, ur = bw, dl = bw, dr = bw;
-            if constexpr (MODE != kModePlain) {
+            if constexpr (MODE == kModeFull || MODE == kModeClause2) {
                 ul = from_lower_lane(uu, bw); ur = from_upper_lane(uu, bw);
                 dl = from_lower_lane(dd, bw); dr = from_upper_lane(dd, bw);
                 if (j == 0) { ul = bw; dl = bw; }
                 if (j == wd - 1) { ur = bw; dr = bw; }
             }
-            const uint32_t v = edge_word<MODE>(cc, east_of(uu, ur), uu, west_of(uu, ul),
-                                               west_of(cc, cl), west_of(dd, dl), dd,
-                                               east_of(dd, dr), east_of(cc, cr)) & vm;
-            if (live[i]) g.out[(int64_t)yy[i] * g.stride + j] = invert ? (v ^ vm) : v;
+            uint32_t* op = g.out + (int64_t)yy[i] * g.stride + j;
+            if constexpr (MODE == kModeDirections) {
+                const uint32_t m = ~cc & vm;
+                if (live[i]) {
+                    op[0] = m & west_of(cc, cl);
+                    op[g.plane] = m & east_of(cc, cr);
+                    op[2 * g.plane] = m & uu;
+                    op[3 * g.plane] = m & dd;
+                }
+            } else {
+                const uint32_t v = edge_word<MODE>(cc, east_of(uu, ur), uu, west_of(uu, ul),
+                                                   west_of(cc, cl), west_of(dd, dl), dd,
+                                                   east_of(dd, dr), east_of(cc, cr)) & vm;
+                if (live[i]) op[0] = invert ? (v ^ vm) : v;
+            }
         }
     }
 }

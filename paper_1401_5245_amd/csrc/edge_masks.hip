@@ -34,6 +34,23 @@ __global__ void __launch_bounds__(512) k_strip(Geom g, int64_t chunks, int rows,
     strip_unit<VW, MODE, Pol>(g, (int)(chunk * kWave * VW), (int)y0, (int)y1, bw, invert != 0);
 }
 
+// Grey image in, edge map out (threshold fused into the strip's loads).
+template <int MODE, class Pol>
+__global__ void __launch_bounds__(512) k_strip_grey(Geom g, int64_t chunks, int rows,
+                                                    int64_t nunits, uint32_t bw, int invert,
+                                                    int vec) {
+    const int wpb = blockDim.x / kWave;
+    const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
+                         wave_uniform(threadIdx.x / kWave);
+    if (unit >= nunits) return;
+    const int64_t strip = unit / chunks;
+    const int64_t chunk = unit - strip * chunks;
+    const int64_t y0 = strip * rows;
+    const int64_t y1 = y0 + rows < g.height ? y0 + rows : g.height;
+    grey_strip_unit<MODE, Pol>(g, (int)(chunk * kWave), (int)y0, (int)y1, bw, invert != 0,
+                               vec != 0);
+}
+
 // One image with rows of <= 32 words, `band` rows per wavefront.
 template <int MODE>
 __global__ void __launch_bounds__(512) k_narrow(Geom g, int64_t band, int64_t nunits, uint32_t bw,
@@ -245,6 +262,10 @@ __global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out
         g.height = d.height;
         g.width = d.width;
         g.wd = (int32_t)wd;
+        g.plane = 0;
+        g.grey = nullptr;
+        g.grey_stride = 0;
+        g.thr = 0;
         const UnitShape s = unit_shape(d.height, d.width, wd, d.offset_words * per,
                                        d.stride_words * per, vmax, rows);
         const int64_t local = u - start[i];
@@ -263,6 +284,43 @@ __global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out
             strip_unit<1, MODE>(g, (int)(chunk * kWave), (int)y0, (int)y1, bw, invert != 0);
         }
     }
+}
+
+// Threshold binarisation + packing (section 7: a grey image is first made
+// binary by a threshold): one 32-bit output word per thread, from 32 grey
+// bytes; a byte >= thr becomes white (1). Rows of `gstride` bytes in,
+// packed rows of `stride` 32-bit words out; bits past the width are 0.
+// VEC: the grey pointer and pitch are 16-byte aligned, so full words load
+// their 32 bytes with two 128-bit loads.
+__device__ __forceinline__ uint32_t pack_ge(uint32_t four, uint32_t thr, int shift) {
+    uint32_t bits = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bits |= (((four >> (8 * b)) & 0xffu) >= thr ? 1u : 0u) << (shift + b);
+    return bits;
+}
+
+template <bool VEC>
+__global__ void __launch_bounds__(256) k_pack(const uint8_t* grey, int64_t gstride, uint32_t* out,
+                                              int64_t stride, int32_t height, int32_t width,
+                                              int32_t wd, uint32_t thr) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)height * wd) return;
+    const int64_t y = t / wd;
+    const int j = (int)(t - y * wd);
+    const uint8_t* rp = grey + y * gstride;
+    const int x0 = 32 * j;
+    uint32_t word = 0;
+    if (VEC && x0 + 32 <= width) {
+        const u32x4 a = *reinterpret_cast<const u32x4*>(rp + x0);
+        const u32x4 b = *reinterpret_cast<const u32x4*>(rp + x0 + 16);
+        word = pack_ge(a.x, thr, 0) | pack_ge(a.y, thr, 4) | pack_ge(a.z, thr, 8) |
+               pack_ge(a.w, thr, 12) | pack_ge(b.x, thr, 16) | pack_ge(b.y, thr, 20) |
+               pack_ge(b.z, thr, 24) | pack_ge(b.w, thr, 28);
+    } else {
+        for (int k = 0; k < 32 && x0 + k < width; ++k)
+            word |= (uint32_t)(rp[x0 + k] >= thr) << k;
+    }
+    out[y * stride + j] = word;
 }
 
 // Plain 128-bit copy: the bandwidth reference.
@@ -447,12 +505,14 @@ int launch_single(const Geom& g, int vw, const edge_launch_cfg& c, uint32_t bw, 
     return launch_strip<MODE, CachedStrip>(g, vw, chunks, c, nunits, blocks, bw, invert, stream);
 }
 
+// Single-image launch. planes = 1 for the edge map; 4 for the fundamental
+// edges (kModeDirections), written plane_words B-bit words apart.
 int image_launch(const void* in, void* out, int64_t height, int64_t width, int64_t stride_words,
                  int word_bits, int border, int mode, uint32_t flags, const edge_launch_cfg* cfg,
-                 void* hip_stream) {
+                 void* hip_stream, int planes = 1, int64_t plane_words = 0) {
     int rc = common_checks(word_bits, border, mode, flags);
     if (rc) return rc;
-    if (height < 0 || width < 0 || stride_words < 0) return EDGE_ERR_INVALID;
+    if (height < 0 || width < 0 || stride_words < 0 || plane_words < 0) return EDGE_ERR_INVALID;
     if (height > 0x7fffffff || width > 0x7fffffff) return EDGE_ERR_INVALID;
     if (cfg && !cfg_ok(*cfg)) return EDGE_ERR_INVALID;
     if (height == 0 || width == 0) return EDGE_OK;
@@ -463,8 +523,12 @@ int image_launch(const void* in, void* out, int64_t height, int64_t width, int64
     const uintptr_t pin = (uintptr_t)in, pout = (uintptr_t)out;
     if (pin % word_bytes || pout % word_bytes) return EDGE_ERR_ALIGN;
     if (stride_words > (int64_t)(INT64_MAX / 8) / height) return EDGE_ERR_INVALID;
-    const uint64_t span = (uint64_t)((height - 1) * stride_words + wd) * word_bytes;
-    if (ranges_overlap(pin, span, pout, span)) return EDGE_ERR_ALIAS;
+    const int64_t span_words = (height - 1) * stride_words + wd;
+    if (planes > 1 && plane_words < span_words) return EDGE_ERR_INVALID;
+    if (planes > 1 && plane_words > (int64_t)(INT64_MAX / 64)) return EDGE_ERR_INVALID;
+    const uint64_t span = (uint64_t)span_words * word_bytes;
+    const uint64_t out_span = (uint64_t)((planes - 1) * plane_words + span_words) * word_bytes;
+    if (ranges_overlap(pin, span, pout, out_span)) return EDGE_ERR_ALIAS;
 
     const int per = word_bits / 32;
     Geom g;
@@ -474,14 +538,20 @@ int image_launch(const void* in, void* out, int64_t height, int64_t width, int64
     g.height = (int32_t)height;
     g.width = (int32_t)width;
     g.wd = (int32_t)(wd * per);
+    g.plane = plane_words * per;
+    g.grey = nullptr;
+    g.grey_stride = 0;
+    g.thr = 0;
     const edge_launch_cfg c = cfg ? *cfg : default_single(height, g.wd);
     int vmax = c.vec_words;
     vmax = std::min(vmax, alignment_words(pin));
     vmax = std::min(vmax, alignment_words(pout));
+    if (planes > 1) vmax = std::min(vmax, alignment_words((uintptr_t)(plane_words * word_bytes)));
     const int vw = pick_vw(g.wd, vmax, 0, g.stride);
     const uint32_t bw = border_word(border);
     const int inv = (flags & EDGE_FLAG_INVERT_OUT) ? 1 : 0;
     hipStream_t s = (hipStream_t)hip_stream;
+    if (planes == 4) return launch_single<kModeDirections>(g, vw, c, bw, 0, s);
     switch (kernel_mode(mode, flags)) {
         case kModePlain: return launch_single<kModePlain>(g, vw, c, bw, inv, s);
         case kModeFull: return launch_single<kModeFull>(g, vw, c, bw, inv, s);
@@ -584,6 +654,33 @@ struct EdgeGraph {
 
 }  // namespace
 
+namespace {
+
+template <int MODE, class Pol>
+int launch_grey(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int invert, int vec,
+                hipStream_t stream) {
+    const int64_t chunks = ceil_div(g.wd, (int64_t)kWave);
+    const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
+    const int64_t blocks = ceil_div(nunits, c.waves_per_block);
+    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL((k_strip_grey<MODE, Pol>), dim3((uint32_t)blocks),
+                       dim3(c.waves_per_block * kWave), 0, stream, g, chunks, c.rows_per_tile,
+                       nunits, bw, invert, vec);
+    return launch_status();
+}
+
+template <int MODE>
+int launch_grey_mode(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int invert, int vec,
+                     hipStream_t stream) {
+    bool stream_mode = c.cache_policy == EDGE_CACHE_STREAM;
+    if (c.cache_policy == EDGE_CACHE_AUTO)
+        stream_mode = (int64_t)g.height * g.grey_stride >= kStreamBytes;
+    if (stream_mode) return launch_grey<MODE, StreamingStrip>(g, c, bw, invert, vec, stream);
+    return launch_grey<MODE, CachedStrip>(g, c, bw, invert, vec, stream);
+}
+
+}  // namespace
+
 // ================================================================== C ABI ===
 
 extern "C" {
@@ -622,6 +719,110 @@ int edge_image_launch(const void* in, void* out, int64_t height, int64_t width,
                       const edge_launch_cfg* cfg, void* hip_stream) {
     return image_launch(in, out, height, width, stride_words, word_bits, border, mode, flags, cfg,
                         hip_stream);
+}
+
+int edge_directions(const void* in, void* out4, int64_t plane_words, int64_t height,
+                    int64_t width, int64_t stride_words, int word_bits, int border,
+                    const edge_launch_cfg* cfg, void* hip_stream) {
+    return image_launch(in, out4, height, width, stride_words, word_bits, border,
+                        EDGE_MODE_MASKS, 0u, cfg, hip_stream, 4, plane_words);
+}
+
+int edge_threshold_pack(const void* grey, int64_t grey_stride_bytes, int threshold, void* out,
+                        int64_t height, int64_t width, int64_t stride_words, int word_bits,
+                        void* hip_stream) {
+    if (word_bits != 32 && word_bits != 64) return EDGE_ERR_INVALID;
+    if (threshold < 0 || threshold > 256) return EDGE_ERR_INVALID;
+    if (height < 0 || width < 0 || stride_words < 0 || grey_stride_bytes < 0)
+        return EDGE_ERR_INVALID;
+    if (height > 0x7fffffff || width > 0x7fffffff) return EDGE_ERR_INVALID;
+    if (height == 0 || width == 0) return EDGE_OK;
+    if (!grey || !out) return EDGE_ERR_INVALID;
+    const int64_t wd = ceil_div(width, word_bits);
+    if (stride_words < wd || grey_stride_bytes < width) return EDGE_ERR_INVALID;
+    const int word_bytes = word_bits / 8;
+    if ((uintptr_t)out % word_bytes) return EDGE_ERR_ALIGN;
+    if (stride_words > (int64_t)(INT64_MAX / 8) / height ||
+        grey_stride_bytes > (int64_t)(INT64_MAX / 2) / height)
+        return EDGE_ERR_INVALID;
+    const uint64_t gspan = (uint64_t)((height - 1) * grey_stride_bytes + width);
+    const uint64_t ospan = (uint64_t)((height - 1) * stride_words + wd) * word_bytes;
+    if (ranges_overlap((uintptr_t)grey, gspan, (uintptr_t)out, ospan)) return EDGE_ERR_ALIAS;
+    const int per = word_bits / 32;
+    const int32_t wd32 = (int32_t)(wd * per);
+    const int64_t threads = height * (int64_t)wd32;
+    const int64_t blocks = ceil_div(threads, 256);
+    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+    const bool vec = (uintptr_t)grey % 16 == 0 && grey_stride_bytes % 16 == 0;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (vec)
+        hipLaunchKernelGGL(k_pack<true>, dim3((uint32_t)blocks), dim3(256), 0, s,
+                           (const uint8_t*)grey, grey_stride_bytes, (uint32_t*)out,
+                           stride_words * per, (int32_t)height, (int32_t)width, wd32,
+                           (uint32_t)threshold);
+    else
+        hipLaunchKernelGGL(k_pack<false>, dim3((uint32_t)blocks), dim3(256), 0, s,
+                           (const uint8_t*)grey, grey_stride_bytes, (uint32_t*)out,
+                           stride_words * per, (int32_t)height, (int32_t)width, wd32,
+                           (uint32_t)threshold);
+    return launch_status();
+}
+
+int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int threshold, void* out,
+                         int64_t height, int64_t width, int64_t stride_words, int word_bits,
+                         int border, int mode, uint32_t flags, const edge_launch_cfg* cfg,
+                         void* hip_stream) {
+    int rc = common_checks(word_bits, border, mode, flags);
+    if (rc) return rc;
+    if (threshold < 0 || threshold > 256) return EDGE_ERR_INVALID;
+    if (height < 0 || width < 0 || stride_words < 0 || grey_stride_bytes < 0)
+        return EDGE_ERR_INVALID;
+    if (height > 0x7fffffff || width > 0x7fffffff) return EDGE_ERR_INVALID;
+    if (cfg && !cfg_ok(*cfg)) return EDGE_ERR_INVALID;
+    if (height == 0 || width == 0) return EDGE_OK;
+    if (!grey || !out) return EDGE_ERR_INVALID;
+    const int64_t wd = ceil_div(width, word_bits);
+    if (stride_words < wd || grey_stride_bytes < width) return EDGE_ERR_INVALID;
+    const int word_bytes = word_bits / 8;
+    if ((uintptr_t)out % word_bytes) return EDGE_ERR_ALIGN;
+    if (stride_words > (int64_t)(INT64_MAX / 8) / height ||
+        grey_stride_bytes > (int64_t)(INT64_MAX / 2) / height)
+        return EDGE_ERR_INVALID;
+    const uint64_t gspan = (uint64_t)((height - 1) * grey_stride_bytes + width);
+    const uint64_t ospan = (uint64_t)((height - 1) * stride_words + wd) * word_bytes;
+    if (ranges_overlap((uintptr_t)grey, gspan, (uintptr_t)out, ospan)) return EDGE_ERR_ALIAS;
+    const int per = word_bits / 32;
+    Geom g;
+    g.in = nullptr;
+    g.out = (uint32_t*)out;
+    g.stride = stride_words * per;
+    g.height = (int32_t)height;
+    g.width = (int32_t)width;
+    g.wd = (int32_t)(wd * per);
+    g.plane = 0;
+    g.grey = (const uint8_t*)grey;
+    g.grey_stride = grey_stride_bytes;
+    g.thr = (uint32_t)threshold;
+    edge_launch_cfg c;
+    if (cfg) {
+        c = *cfg;
+    } else {
+        c.vec_words = 1;
+        c.blocks_per_cu = 1;
+        c.cache_policy = EDGE_CACHE_AUTO;
+        const int64_t chunks = ceil_div(g.wd, (int64_t)kWave);
+        c.rows_per_tile = (int32_t)pow2_floor(std::max<int64_t>(2, std::min<int64_t>(256, chunks * height / 2048)));
+        c.waves_per_block = c.rows_per_tile >= 16 ? 8 : 4;
+    }
+    const int vec = (uintptr_t)grey % 16 == 0 && grey_stride_bytes % 16 == 0;
+    const uint32_t bw = border_word(border);
+    const int inv = (flags & EDGE_FLAG_INVERT_OUT) ? 1 : 0;
+    hipStream_t s = (hipStream_t)hip_stream;
+    switch (kernel_mode(mode, flags)) {
+        case kModePlain: return launch_grey_mode<kModePlain>(g, c, bw, inv, vec, s);
+        case kModeFull: return launch_grey_mode<kModeFull>(g, c, bw, inv, vec, s);
+        default: return launch_grey_mode<kModeClause2>(g, c, bw, inv, vec, s);
+    }
 }
 
 int edge_default_cfg(int64_t height, int64_t width, int word_bits, int mode, int batch,

@@ -249,3 +249,20 @@ def serving_pool(n: int = 64, seed: int = 5, side=(64, 4096), q: float = 0.3) ->
 def log_uniform_sides(rng: np.random.Generator, n: int, side) -> np.ndarray:
     lo, hi = math.log(side[0]), math.log(side[1])
     return np.rint(np.exp(rng.uniform(lo, hi, size=n))).astype(np.int64)
+
+
+def grey_image(height: int, width: int, seed: int, blobs: int = 24) -> np.ndarray:
+    """A grey uint8 image standing in for the photograph of section 7:
+    a smooth field of random Gaussian blobs over a gradient, plus noise.
+    (Grey values are not binary; threshold them first.)"""
+    rng = np.random.default_rng(seed)
+    yy = np.linspace(0.0, 1.0, height, dtype=np.float32)[:, None]
+    xx = np.linspace(0.0, 1.0, width, dtype=np.float32)[None, :]
+    f = 0.3 * xx + 0.2 * yy
+    for _ in range(blobs):
+        cy, cx = rng.uniform(0, 1, size=2)
+        r = rng.uniform(0.02, 0.2)
+        f = f + rng.uniform(-0.6, 0.6) * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * r * r))
+    f = f + rng.normal(0.0, 0.03, size=(height, width)).astype(np.float32)
+    lo, hi = float(f.min()), float(f.max())
+    return np.clip((f - lo) / max(hi - lo, 1e-6) * 255.0, 0, 255).astype(np.uint8)

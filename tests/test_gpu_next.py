@@ -1,0 +1,126 @@
+"""Direction planes (section 4) and threshold packing (section 7) on the
+GPU, bit-exact against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import images, pack_rows, row_words, unpack_rows
+from tests.gpu_util import assert_same, log, to_device_words
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 1), (1, 70), (5, 31), (3, 33), (40, 257), (17, 1000), (9, 2049), (33, 4100),
+          (70, 8193)]
+
+
+@pytest.mark.parametrize("word_bits", [32, 64])
+@pytest.mark.parametrize("H,W", SHAPES)
+def test_direction_planes(word_bits, H, W):
+    import paper_1401_5245_amd as em
+    img = images.bernoulli_image(H, W, 0.45, seed=H * 31 + W)
+    for border in ("white", "black"):
+        for extra in (0, 3):
+            S = row_words(W, word_bits) + extra
+            words = pack_rows(img, word_bits, S, pad="random", seed=W)
+            inp = to_device_words(words)
+            plane = H * S + 5                        # planes with a gap between them
+            dt = inp.dtype
+            out = torch.full((4 * plane,), -1, dtype=dt, device="cuda")
+            em.edge_directions(inp, out, H, W, border=border, stride_words=S)
+            mask = torch.zeros_like(inp)
+            em.edge_masks(inp, mask, H, W, border=border)
+            torch.cuda.synchronize()
+            host = out.cpu().numpy().view(words.dtype)
+            want = oracle.fundamental_edges(img, border=border)
+            ors = np.zeros((H, W), np.uint8)
+            for k in range(4):
+                pw = host[k * plane:k * plane + H * S].reshape(H, S)
+                got = unpack_rows(pw, W)
+                assert_same(got, want[k], f"plane {oracle.DIRECTIONS[k]} B={word_bits} {border}")
+                assert (pw[:, row_words(W, word_bits):] == ~words.dtype.type(0)).all()
+                ors |= got
+            assert_same(ors, unpack_rows(mask.cpu().numpy().view(words.dtype), W), "OR of planes")
+
+
+@pytest.mark.parametrize("cfg", [dict(vec_words=1, rows_per_tile=3, waves_per_block=2),
+                                 dict(vec_words=4, rows_per_tile=16, waves_per_block=8,
+                                      cache_policy=2)])
+def test_direction_planes_cfgs(cfg):
+    import paper_1401_5245_amd as em
+    img = images.glyph_page(300, 3000, seed=8, noise=0.02)
+    words = pack_rows(img, 64)
+    inp = to_device_words(words)
+    out = torch.empty((4,) + tuple(inp.shape), dtype=inp.dtype, device="cuda")
+    em.edge_directions(inp, out, *img.shape, cfg=cfg)
+    torch.cuda.synchronize()
+    want = oracle.fundamental_edges(img)
+    host = out.cpu().numpy().view(np.uint64)
+    for k in range(4):
+        assert_same(unpack_rows(host[k], img.shape[1]), want[k], oracle.DIRECTIONS[k])
+
+
+@pytest.mark.parametrize("word_bits", [32, 64])
+@pytest.mark.parametrize("H,W", [(1, 1), (3, 31), (5, 32), (7, 33), (20, 100), (64, 1000),
+                                 (9, 4097)])
+def test_threshold_pack(word_bits, H, W):
+    import paper_1401_5245_amd as em
+    grey = images.grey_image(H, W, seed=H + W)
+    for gpad in (0, 16, 5):                        # aligned and unaligned grey pitches
+        gs = W + gpad
+        g = np.zeros((H, gs), np.uint8)
+        g[:, :W] = grey
+        gt = torch.from_numpy(g).cuda()
+        for t in (0, 1, 97, 128, 255, 256):
+            S = row_words(W, word_bits) + 1
+            out = to_device_words(np.full((H, S), 0x5A5A5A5A, dtype=np.uint32 if word_bits == 32
+                                          else np.uint64))
+            em.threshold_pack(gt, out, H, W, t, grey_stride=gs, stride_words=S)
+            torch.cuda.synchronize()
+            host = out.cpu().numpy().view(np.uint32 if word_bits == 32 else np.uint64)
+            assert_same(unpack_rows(host, W), oracle.threshold(grey, t), f"t={t} gs={gs}")
+            np.testing.assert_array_equal(pack_rows(oracle.threshold(grey, t), word_bits, S)[:, :-1],
+                                          host[:, :-1])
+
+
+@pytest.mark.parametrize("word_bits", [32, 64])
+@pytest.mark.parametrize("H,W", [(1, 1), (2, 31), (5, 33), (9, 1000), (4, 2048), (7, 2049),
+                                 (33, 4100), (3, 8200)])
+def test_threshold_edges_fused(word_bits, H, W):
+    import paper_1401_5245_amd as em
+    grey = images.grey_image(H, W, seed=2 * H + W)
+    for gpad in (0, 16, 3):
+        gs = W + gpad
+        g = np.zeros((H, gs), np.uint8)
+        g[:, :W] = grey
+        gt = torch.from_numpy(g).cuda()
+        for t in (0, 100, 128, 256):
+            binary = oracle.threshold(grey, t)
+            for border, mode, c2, inv in (("white", "masks", False, False),
+                                          ("black", "full", True, False),
+                                          ("white", "full", False, True)):
+                S = row_words(W, word_bits)
+                out = to_device_words(np.zeros((H, S), dtype=np.uint32 if word_bits == 32
+                                               else np.uint64))
+                em.threshold_edges(gt, out, H, W, t, grey_stride=gs, border=border, mode=mode,
+                                   clause2_only=c2, invert=inv)
+                torch.cuda.synchronize()
+                host = out.cpu().numpy().view(np.uint32 if word_bits == 32 else np.uint64)
+                clauses = oracle.CLAUSE2 if c2 else (3 if mode == "full" else oracle.CLAUSE1)
+                want = oracle.edge(binary, border=border, clauses=clauses, invert=inv)
+                assert_same(unpack_rows(host, W), want, f"t={t} gs={gs} {border} {mode}")
+
+
+@pytest.mark.parametrize("rows,waves,cache", [(1, 1, 1), (3, 2, 2), (16, 8, 1), (64, 4, 2)])
+def test_threshold_edges_cfgs(rows, waves, cache):
+    import paper_1401_5245_amd as em
+    H, W = 130, 5000
+    grey = images.grey_image(H, W, seed=rows)
+    gt = torch.from_numpy(np.ascontiguousarray(grey)).cuda()
+    S = row_words(W, 64)
+    out = torch.zeros((H, S), dtype=torch.int64, device="cuda")
+    em.threshold_edges(gt, out, H, W, 120, cfg=dict(vec_words=1, rows_per_tile=rows,
+                                                    waves_per_block=waves, cache_policy=cache))
+    torch.cuda.synchronize()
+    want = oracle.edge(oracle.threshold(grey, 120))
+    assert_same(unpack_rows(out.cpu().numpy().view(np.uint64), W), want, "cfg")
