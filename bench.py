@@ -46,6 +46,8 @@ def parse():
                    help="run only the serving sweep (prints its JSON)")
     p.add_argument("--batch-only", action="store_true",
                    help="run only the batched-crops workload (prints its JSON)")
+    p.add_argument("--next-only", action="store_true",
+                   help="run only the widened rows (prints their JSON)")
     p.add_argument("--streams", default="1,2,4",
                    help="stream counts the headline graph is captured with")
     return p.parse_args()
@@ -435,6 +437,85 @@ def serving(torch, em, p99_bound_ms=20.0, budget=4 << 30):
     return out
 
 
+def next_rows(torch, em, tm, steps):
+    """The widened rows at 8192^2: the paper's unfused stages against the
+    fused kernel, the four fundamental-edge planes, and thresholding a grey
+    image (two passes against the fused pass). Every output is checked
+    against the oracle on the whole image."""
+    from synth import images, pack_rows, unpack_rows
+    import oracle
+    H = W = 8192
+    img = images.glyph_page(H, W, seed=2)
+    words = pack_rows(img, 64)
+    inp = words_tensor(torch, words)
+    out = torch.empty_like(inp)
+    px = H * W
+    packed_bytes = H * (W // 8)
+    res = {}
+
+    def graph_time(fns, reps):
+        g = graph_of(torch, None, nstreams=1, fns=fns)
+        g.replay()
+        ms = tm.per_call_ms(lambda i: g.replay(), reps) / len(fns)
+        del g
+        return ms
+
+    # NEXT-1: unfused stages
+    scratch = torch.empty(em.staged_scratch_bytes(H, W // 64, 64) // 8, dtype=torch.int64,
+                          device="cuda")
+    em.edge_masks_staged(inp, out, H, W, scratch)
+    torch.cuda.synchronize()
+    want = oracle.edge(img)
+    ok = bool(np.array_equal(unpack_rows(out.cpu().numpy().view(np.uint64), W), want))
+    ms_staged = graph_time([lambda: em.edge_masks_staged(inp, out, H, W, scratch)] * 10, 3)
+    ms_fused = graph_time([lambda: em.edge_image(inp, out, H, W, cfg="tuned")] * 10, 3)
+    res["staged_vs_fused"] = {
+        "workload": "8192x8192 glyph page, uint64: the three stages as 8 passes vs one fused pass",
+        "ms_staged": round(ms_staged, 4), "ms_fused": round(ms_fused, 4),
+        "fusion_speedup": round(ms_staged / ms_fused, 2),
+        "staged_bytes_moved": 23 * packed_bytes, "fused_bytes_moved": 2 * packed_bytes,
+        "staged_gbs_of_moved_bytes": round(23 * packed_bytes / (ms_staged * 1e-3) / 1e9, 1),
+        "bit_exact": ok}
+    del scratch
+    # NEXT-3: direction planes
+    out4 = torch.empty((4,) + tuple(inp.shape), dtype=inp.dtype, device="cuda")
+    em.edge_directions(inp, out4, H, W)
+    torch.cuda.synchronize()
+    planes = out4.cpu().numpy().view(np.uint64)
+    fe = oracle.fundamental_edges(img)
+    ok = all(np.array_equal(unpack_rows(planes[k], W), fe[k]) for k in range(4))
+    ms_dir = graph_time([lambda: em.edge_directions(inp, out4, H, W)] * 10, 3)
+    res["directions"] = {
+        "workload": "8192x8192 glyph page, uint64: four fundamental-edge planes (left, right, up, "
+                    "down)", "ms": round(ms_dir, 4),
+        "gbs": round(5 * packed_bytes / (ms_dir * 1e-3) / 1e9, 1), "bytes_moved": 5 * packed_bytes,
+        "bit_exact": ok}
+    del out4
+    # NEXT-2: grey image -> threshold -> edges
+    grey = images.grey_image(H, W, seed=7)
+    gt = torch.from_numpy(grey).cuda()
+    binary = torch.empty_like(inp)
+    em.threshold_edges(gt, out, H, W, 128)
+    torch.cuda.synchronize()
+    want = oracle.edge(oracle.threshold(grey, 128))
+    ok = bool(np.array_equal(unpack_rows(out.cpu().numpy().view(np.uint64), W), want))
+    ms_fused_t = graph_time([lambda: em.threshold_edges(gt, out, H, W, 128)] * 10, 3)
+
+    def two_pass():
+        em.threshold_pack(gt, binary, H, W, 128)
+        em.edge_image(binary, out, H, W, cfg="tuned")
+
+    ms_two = graph_time([two_pass] * 10, 3)
+    res["threshold_edges"] = {
+        "workload": "8192x8192 grey image (smooth blobs + noise, seed 7), threshold 128, uint64",
+        "ms_fused": round(ms_fused_t, 4), "ms_two_pass": round(ms_two, 4),
+        "gbs_fused": round((px + packed_bytes) / (ms_fused_t * 1e-3) / 1e9, 1),
+        "gpx_s_fused": round(px / (ms_fused_t * 1e-3) / 1e9, 1), "bit_exact": ok}
+    del gt, binary, inp, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(img, seconds):
     import oracle
     t0 = time.perf_counter()
@@ -468,6 +549,9 @@ def main():
         return
     if args.batch_only:
         print(json.dumps(batched_crops(torch, em, tm, args.steps)), flush=True)
+        return
+    if args.next_only:
+        print(json.dumps(next_rows(torch, em, tm, args.steps)), flush=True)
         return
     counts = tuple(sorted({1} | {int(v) for v in args.streams.split(",")}))
     img, per_streams, eager_ms, timed, exact, hcfg = headline(torch, em, tm, args.steps,
@@ -516,6 +600,8 @@ def main():
         extra["full_16384"] = full_16384(torch, em, tm, 50)
         log("config: batched crops")
         extra["batched_4096"] = batched_crops(torch, em, tm, args.steps)
+        log("config: next rows (staged ablation, direction planes, threshold)")
+        extra["next_rows"] = next_rows(torch, em, tm, args.steps)
         log("config: serving")
         extra["serving"] = serving(torch, em)
         res["extra"] = extra

@@ -174,6 +174,19 @@ int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int thresh
                          int border, int mode, uint32_t flags, const edge_launch_cfg* cfg,
                          void* hip_stream);
 
+/* The paper's three stages as separate whole-image passes, the unfused
+ * form of edge_masks kept as an ablation: mask = negative image
+ * (section 3); four fundamental edges = mask AND the image shifted by one
+ * pixel (section 4); three ORs into the left edge (section 5; the display
+ * inversion is left out). Eight launches, about 23 image-sized transfers
+ * against 2 for the fused kernel. Same output as edge_masks.
+ * scratch: device buffer of >= 4 * height * stride_words * word_bits / 8
+ * bytes (mask and three edge planes), 4-byte aligned, disjoint from in and
+ * out. */
+int edge_masks_staged(const void* in, void* out, void* scratch, int64_t scratch_bytes,
+                      int64_t height, int64_t width, int64_t stride_words, int word_bits,
+                      int border, void* hip_stream);
+
 /* Built-in launch configuration for an image shape (batch != 0: for the
  * persistent batch kernel). Returns EDGE_OK and fills *cfg_out. */
 int edge_default_cfg(int64_t height, int64_t width, int word_bits, int mode,

@@ -162,6 +162,22 @@ def threshold_edges(grey: torch.Tensor, out: torch.Tensor, height: int, width: i
     return out
 
 
+def staged_scratch_bytes(height: int, stride_words: int, word_bits: int) -> int:
+    return 4 * height * stride_words * word_bits // 8
+
+
+def edge_masks_staged(inp: torch.Tensor, out: torch.Tensor, height: int, width: int,
+                      scratch: torch.Tensor, *, border: str = "white", stride_words=None,
+                      stream=None) -> torch.Tensor:
+    """The paper's three stages as eight separate passes (the unfused
+    ablation of edge_masks; same output)."""
+    wb, s = _image_args(inp, out, height, width, stride_words)
+    check(_lib.edge_masks_staged(inp.data_ptr(), out.data_ptr(), scratch.data_ptr(),
+                                 scratch.numel() * scratch.element_size(), height, width, s, wb,
+                                 BORDERS[border], stream_handle(stream)))
+    return out
+
+
 def default_cfg(height: int, width: int, word_bits: int, mode: str = "masks",
                 batch: bool = False) -> dict:
     c = EdgeLaunchCfg()

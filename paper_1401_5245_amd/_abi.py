@@ -76,6 +76,8 @@ _SIGNATURES = {
     "edge_threshold_edges": (ctypes.c_int, [c_vp, c_i64, ctypes.c_int, c_vp, c_i64, c_i64, c_i64,
                                             ctypes.c_int, ctypes.c_int, ctypes.c_int, c_u32,
                                             ctypes.POINTER(EdgeLaunchCfg), c_vp]),
+    "edge_masks_staged": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_i64,
+                                         ctypes.c_int, ctypes.c_int, c_vp]),
     "edge_default_cfg": (ctypes.c_int, [c_i64, c_i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.POINTER(EdgeLaunchCfg)]),
     "edge_batch_workspace_bytes": (c_i64, [c_i32]),

@@ -323,6 +323,50 @@ __global__ void __launch_bounds__(256) k_pack(const uint8_t* grey, int64_t gstri
     out[y * stride + j] = word;
 }
 
+// The paper's method as separate whole-image passes (sections 3-5), each a
+// block operation over 32-bit words, one word per thread. Used as the
+// unfused ablation of the fused kernels. Pixels past the width read as the
+// border colour (bw) in every pass.
+enum { kStageMask = 0, kStageLeft, kStageRight, kStageUp, kStageDown, kStageOr, kStageOrLast };
+
+__device__ __forceinline__ uint32_t stage_pixel_word(const uint32_t* in, int64_t stride,
+                                                     int32_t height, int32_t width, int32_t wd,
+                                                     int64_t y, int j, uint32_t bw) {
+    if (y < 0 || y >= height || j < 0 || j >= wd) return bw;
+    const uint32_t vm = valid_bits(j, width);
+    return (in[y * stride + j] & vm) | (bw & ~vm);
+}
+
+template <int STAGE>
+__global__ void __launch_bounds__(256) k_stage(const uint32_t* img, const uint32_t* src,
+                                               uint32_t* dst, int64_t stride, int32_t height,
+                                               int32_t width, int32_t wd, uint32_t bw) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)height * wd) return;
+    const int64_t y = t / wd;
+    const int j = (int)(t - y * wd);
+    const int64_t o = y * stride + j;
+    if constexpr (STAGE == kStageMask) {                 // section 3: the negative image
+        dst[o] = ~stage_pixel_word(img, stride, height, width, wd, y, j, bw);
+    } else if constexpr (STAGE <= kStageDown) {          // section 4: shifted image AND mask
+        const uint32_t c = stage_pixel_word(img, stride, height, width, wd, y, j, bw);
+        uint32_t shifted;
+        if constexpr (STAGE == kStageLeft)               // image shifted right: sees x - 1
+            shifted = west_of(c, stage_pixel_word(img, stride, height, width, wd, y, j - 1, bw));
+        else if constexpr (STAGE == kStageRight)         // image shifted left: sees x + 1
+            shifted = east_of(c, stage_pixel_word(img, stride, height, width, wd, y, j + 1, bw));
+        else if constexpr (STAGE == kStageUp)            // image shifted down: sees y - 1
+            shifted = stage_pixel_word(img, stride, height, width, wd, y - 1, j, bw);
+        else                                             // image shifted up: sees y + 1
+            shifted = stage_pixel_word(img, stride, height, width, wd, y + 1, j, bw);
+        dst[o] = src[o] & shifted;
+    } else {                                             // section 5: OR of the edges
+        uint32_t v = dst[o] | src[o];
+        if constexpr (STAGE == kStageOrLast) v &= valid_bits(j, width);
+        dst[o] = v;
+    }
+}
+
 // Plain 128-bit copy: the bandwidth reference.
 __global__ void __launch_bounds__(256) k_copy(const u32x4* in, u32x4* out, int64_t n16) {
     constexpr int kPer = 4;
@@ -681,6 +725,20 @@ int launch_grey_mode(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int i
 
 }  // namespace
 
+namespace {
+
+template <int STAGE>
+int launch_stage(const uint32_t* img, const uint32_t* src, uint32_t* dst, int64_t stride,
+                 int32_t height, int32_t width, int32_t wd, uint32_t bw, hipStream_t s) {
+    const int64_t blocks = ceil_div((int64_t)height * wd, 256);
+    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(k_stage<STAGE>, dim3((uint32_t)blocks), dim3(256), 0, s, img, src, dst,
+                       stride, height, width, wd, bw);
+    return launch_status();
+}
+
+}  // namespace
+
 // ================================================================== C ABI ===
 
 extern "C" {
@@ -823,6 +881,50 @@ int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int thresh
         case kModeFull: return launch_grey_mode<kModeFull>(g, c, bw, inv, vec, s);
         default: return launch_grey_mode<kModeClause2>(g, c, bw, inv, vec, s);
     }
+}
+
+int edge_masks_staged(const void* in, void* out, void* scratch, int64_t scratch_bytes,
+                      int64_t height, int64_t width, int64_t stride_words, int word_bits,
+                      int border, void* hip_stream) {
+    if (word_bits != 32 && word_bits != 64) return EDGE_ERR_INVALID;
+    if (border != EDGE_BORDER_WHITE && border != EDGE_BORDER_BLACK) return EDGE_ERR_INVALID;
+    if (height < 0 || width < 0 || stride_words < 0 || scratch_bytes < 0) return EDGE_ERR_INVALID;
+    if (height > 0x7fffffff || width > 0x7fffffff) return EDGE_ERR_INVALID;
+    if (height == 0 || width == 0) return EDGE_OK;
+    if (!in || !out) return EDGE_ERR_INVALID;
+    const int64_t wd = ceil_div(width, word_bits);
+    if (stride_words < wd) return EDGE_ERR_INVALID;
+    const int word_bytes = word_bits / 8;
+    if ((uintptr_t)in % word_bytes || (uintptr_t)out % word_bytes) return EDGE_ERR_ALIGN;
+    if (stride_words > (int64_t)(INT64_MAX / 64) / height) return EDGE_ERR_INVALID;
+    const int64_t plane = height * stride_words * word_bytes;     // bytes per scratch plane
+    const uint64_t span = (uint64_t)((height - 1) * stride_words + wd) * word_bytes;
+    if (!scratch || scratch_bytes < 4 * plane || (uintptr_t)scratch % 4)
+        return EDGE_ERR_WORKSPACE;
+    const uintptr_t pin = (uintptr_t)in, pout = (uintptr_t)out, ps = (uintptr_t)scratch;
+    if (ranges_overlap(pin, span, pout, span) || ranges_overlap(pin, span, ps, 4 * plane) ||
+        ranges_overlap(pout, span, ps, 4 * plane))
+        return EDGE_ERR_ALIAS;
+    const int per = word_bits / 32;
+    const int64_t stride = stride_words * per;
+    const int32_t wd32 = (int32_t)(wd * per), H = (int32_t)height, W = (int32_t)width;
+    const uint32_t bw = border_word(border);
+    const uint32_t* img = (const uint32_t*)in;
+    uint32_t* mask = (uint32_t*)scratch;
+    uint32_t* f_right = (uint32_t*)(ps + plane);
+    uint32_t* f_up = (uint32_t*)(ps + 2 * plane);
+    uint32_t* f_down = (uint32_t*)(ps + 3 * plane);
+    uint32_t* f_left = (uint32_t*)out;                  // the left edge accumulates the OR
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc;
+    if ((rc = launch_stage<kStageMask>(img, nullptr, mask, stride, H, W, wd32, bw, s))) return rc;
+    if ((rc = launch_stage<kStageLeft>(img, mask, f_left, stride, H, W, wd32, bw, s))) return rc;
+    if ((rc = launch_stage<kStageRight>(img, mask, f_right, stride, H, W, wd32, bw, s))) return rc;
+    if ((rc = launch_stage<kStageUp>(img, mask, f_up, stride, H, W, wd32, bw, s))) return rc;
+    if ((rc = launch_stage<kStageDown>(img, mask, f_down, stride, H, W, wd32, bw, s))) return rc;
+    if ((rc = launch_stage<kStageOr>(img, f_right, f_left, stride, H, W, wd32, bw, s))) return rc;
+    if ((rc = launch_stage<kStageOr>(img, f_up, f_left, stride, H, W, wd32, bw, s))) return rc;
+    return launch_stage<kStageOrLast>(img, f_down, f_left, stride, H, W, wd32, bw, s);
 }
 
 int edge_default_cfg(int64_t height, int64_t width, int word_bits, int mode, int batch,

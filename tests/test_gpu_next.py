@@ -124,3 +124,26 @@ def test_threshold_edges_cfgs(rows, waves, cache):
     torch.cuda.synchronize()
     want = oracle.edge(oracle.threshold(grey, 120))
     assert_same(unpack_rows(out.cpu().numpy().view(np.uint64), W), want, "cfg")
+
+
+@pytest.mark.parametrize("word_bits", [32, 64])
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 65), (6, 31), (5, 100), (40, 1000), (9, 4100)])
+def test_staged_pipeline_equals_fused_and_oracle(word_bits, H, W):
+    import paper_1401_5245_amd as em
+    img = images.bernoulli_image(H, W, 0.5, seed=H + 7 * W)
+    for border in ("white", "black"):
+        S = row_words(W, word_bits) + 1
+        words = pack_rows(img, word_bits, S, pad="random", seed=3)
+        inp = to_device_words(words)
+        out = torch.full_like(inp, -1)
+        scratch = torch.full((em.staged_scratch_bytes(H, S, word_bits) // 4,), 7,
+                             dtype=torch.int32, device="cuda")
+        em.edge_masks_staged(inp, out, H, W, scratch, border=border)
+        fused = torch.zeros_like(inp)
+        em.edge_masks(inp, fused, H, W, border=border)
+        torch.cuda.synchronize()
+        host = out.cpu().numpy().view(words.dtype)
+        assert_same(unpack_rows(host, W), oracle.edge(img, border=border), f"staged {border}")
+        wd = row_words(W, word_bits)
+        np.testing.assert_array_equal(host[:, :wd], fused.cpu().numpy().view(words.dtype)[:, :wd])
+        assert (host[:, wd:] == ~words.dtype.type(0)).all()        # stride padding untouched
