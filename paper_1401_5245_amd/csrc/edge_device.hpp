@@ -262,18 +262,15 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
                 r.b[0] = Pol::nt_load ? __builtin_nontemporal_load(vp) : vp[0];
                 r.b[1] = Pol::nt_load ? __builtin_nontemporal_load(vp + 1) : vp[1];
             } else {
-                uint32_t d[8];
+                // byte by byte from clamped addresses, thresholded at once
+                // (the packed word goes in b[0].x)
+                uint32_t word = 0;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    d[q] = 0;
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int64_t x = 32ll * jl + 4 * q + b;
-                        d[q] |= (uint32_t)rp[x < g.width ? x : g.width - 1] << (8 * b);
-                    }
+                for (int k = 0; k < 32; ++k) {
+                    const int64_t x = 32ll * jl + k;
+                    word |= (uint32_t)(rp[x < g.width ? x : g.width - 1] >= g.thr) << k;
                 }
-                r.b[0].x = d[0]; r.b[0].y = d[1]; r.b[0].z = d[2]; r.b[0].w = d[3];
-                r.b[1].x = d[4]; r.b[1].y = d[5]; r.b[1].z = d[6]; r.b[1].w = d[7];
+                r.b[0].x = word;
             }
             if constexpr (EDGES) r.e = rp[has_e ? xe_load : 0];
             else r.e = 0;
@@ -300,7 +297,8 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
         Row o;
         uint32_t e;
         if constexpr (GREY) {
-            o.c[0] = inside ? ((threshold_word(r.b[0], r.b[1], g.thr) & vm[0]) | om[0]) : bw;
+            const uint32_t word = WHOLE ? threshold_word(r.b[0], r.b[1], g.thr) : r.b[0].x;
+            o.c[0] = inside ? ((word & vm[0]) | om[0]) : bw;
             // only the neighbour pixel's bit is used by the carries
             e = (EDGES && inside && has_e) ? (r.e >= g.thr ? 0xffffffffu : 0u) : bw;
         } else {
@@ -394,19 +392,23 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
     }
 }
 
-// Grey input (threshold then edges), one word per lane. vec: the grey
-// pointer and pitch are 16-byte aligned.
-template <int MODE, class Pol>
+// Grey input (threshold then edges), one word per lane. TAIL = false: the
+// span's bytes all lie in the row and rows are 16-byte aligned (128-bit
+// loads); TAIL = true: bytes load one by one from clamped addresses, with
+// one row in flight (the row's last chunk, or unaligned rows). The two run
+// as separate launches so the byte path does not set the register budget of
+// the aligned one.
+template <int MODE, class Pol, bool TAIL>
 __device__ __forceinline__ void grey_strip_unit(const Geom& g, int j0, int y0, int y1,
-                                                uint32_t bw, bool invert, bool vec) {
-    const bool whole = vec && (int64_t)(j0 + kWave) * 32 <= g.width;
+                                                uint32_t bw, bool invert) {
+    using Tail = StripPolicy<1, false, false>;
     const bool edges = j0 > 0 || j0 + kWave < g.wd;
-    if (whole) {
+    if constexpr (!TAIL) {
         if (edges) strip_body<1, MODE, true, true, Pol, true>(g, j0, y0, y1, bw, invert);
         else strip_body<1, MODE, true, false, Pol, true>(g, j0, y0, y1, bw, invert);
     } else {
-        if (edges) strip_body<1, MODE, false, true, Pol, true>(g, j0, y0, y1, bw, invert);
-        else strip_body<1, MODE, false, false, Pol, true>(g, j0, y0, y1, bw, invert);
+        if (edges) strip_body<1, MODE, false, true, Tail, true>(g, j0, y0, y1, bw, invert);
+        else strip_body<1, MODE, false, false, Tail, true>(g, j0, y0, y1, bw, invert);
     }
 }
 

@@ -35,20 +35,21 @@ __global__ void __launch_bounds__(512) k_strip(Geom g, int64_t chunks, int rows,
 }
 
 // Grey image in, edge map out (threshold fused into the strip's loads).
-template <int MODE, class Pol>
-__global__ void __launch_bounds__(512) k_strip_grey(Geom g, int64_t chunks, int rows,
-                                                    int64_t nunits, uint32_t bw, int invert,
-                                                    int vec) {
+// This launch covers word chunks [chunk0, chunk0 + chunks) of every row.
+template <int MODE, class Pol, bool TAIL>
+__global__ void __launch_bounds__(512) k_strip_grey(Geom g, int64_t chunk0, int64_t chunks,
+                                                    int rows, int64_t nunits, uint32_t bw,
+                                                    int invert) {
     const int wpb = blockDim.x / kWave;
     const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
                          wave_uniform(threadIdx.x / kWave);
     if (unit >= nunits) return;
     const int64_t strip = unit / chunks;
-    const int64_t chunk = unit - strip * chunks;
+    const int64_t chunk = chunk0 + (unit - strip * chunks);
     const int64_t y0 = strip * rows;
     const int64_t y1 = y0 + rows < g.height ? y0 + rows : g.height;
-    grey_strip_unit<MODE, Pol>(g, (int)(chunk * kWave), (int)y0, (int)y1, bw, invert != 0,
-                               vec != 0);
+    grey_strip_unit<MODE, Pol, TAIL>(g, (int)(chunk * kWave), (int)y0, (int)y1, bw,
+                                     invert != 0);
 }
 
 // One image with rows of <= 32 words, `band` rows per wavefront.
@@ -700,17 +701,29 @@ struct EdgeGraph {
 
 namespace {
 
+template <int MODE, class Pol, bool TAIL>
+int launch_grey_part(const Geom& g, const edge_launch_cfg& c, int64_t chunk0, int64_t chunks,
+                     uint32_t bw, int invert, hipStream_t stream) {
+    if (chunks <= 0) return EDGE_OK;
+    const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
+    const int64_t blocks = ceil_div(nunits, c.waves_per_block);
+    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL((k_strip_grey<MODE, Pol, TAIL>), dim3((uint32_t)blocks),
+                       dim3(c.waves_per_block * kWave), 0, stream, g, chunk0, chunks,
+                       c.rows_per_tile, nunits, bw, invert);
+    return launch_status();
+}
+
+// Chunks whose 64 words of grey bytes lie wholly inside the row (and rows
+// 16-byte aligned) take the 128-bit path; the rest the byte path.
 template <int MODE, class Pol>
 int launch_grey(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int invert, int vec,
                 hipStream_t stream) {
     const int64_t chunks = ceil_div(g.wd, (int64_t)kWave);
-    const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
-    const int64_t blocks = ceil_div(nunits, c.waves_per_block);
-    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL((k_strip_grey<MODE, Pol>), dim3((uint32_t)blocks),
-                       dim3(c.waves_per_block * kWave), 0, stream, g, chunks, c.rows_per_tile,
-                       nunits, bw, invert, vec);
-    return launch_status();
+    const int64_t whole = vec ? std::min<int64_t>(chunks, g.width / (32 * kWave)) : 0;
+    int rc = launch_grey_part<MODE, Pol, false>(g, c, 0, whole, bw, invert, stream);
+    if (rc) return rc;
+    return launch_grey_part<MODE, Pol, true>(g, c, whole, chunks - whole, bw, invert, stream);
 }
 
 template <int MODE>
