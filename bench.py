@@ -48,6 +48,9 @@ def parse():
                    help="run only the batched-crops workload (prints its JSON)")
     p.add_argument("--next-only", action="store_true",
                    help="run only the widened rows (prints their JSON)")
+    p.add_argument("--only", type=lambda v: v.split(","),
+                   help="comma-separated sections to run alone, printing their JSON "
+                        "(for profiling): " + ", ".join(SECTIONS))
     p.add_argument("--streams", default="1,2,4",
                    help="stream counts the headline graph is captured with")
     return p.parse_args()
@@ -223,6 +226,8 @@ def headline(torch, em, tm, steps, warmup, stream_counts=(1, 2, 4)):
             g.replay()
         torch.cuda.synchronize()
         per_streams[ns] = tm.per_call_ms(lambda i: g.replay(), reps) / NB
+        if ns == 1:     # repeat the timed region: spread over ten trials
+            trials = [tm.per_call_ms(lambda i: g.replay(), reps) / NB for _ in range(10)]
         ok = all(np.array_equal(o.cpu().numpy().view(np.uint64), ref) for o in outs[::7])
         replay_ok &= ok
         log(f"graph on {ns} stream(s): {per_streams[ns] * 1e3:.2f} us/launch, "
@@ -230,7 +235,7 @@ def headline(torch, em, tm, steps, warmup, stream_counts=(1, 2, 4)):
         del g
     del ins, outs, launches
     torch.cuda.empty_cache()
-    return img, per_streams, eager_ms, reps * NB, exact and replay_ok, cfg
+    return img, per_streams, eager_ms, reps * NB, exact and replay_ok, cfg, trials
 
 
 def copy_ceiling(torch, em, tm, nbytes, nb, steps):
@@ -516,6 +521,213 @@ def next_rows(torch, em, tm, steps):
     return res
 
 
+def random_words(torch, side: int):
+    """A side x side image of independent fair random bits (Bernoulli(0.5)),
+    packed uint64, drawn on the device."""
+    return torch.randint(0, 256, (side * side // 8,), dtype=torch.uint8,
+                         device="cuda").view(torch.int64).view(side, side // 64)
+
+
+def sample_check(inp, out, height, width, rows, word_bits=64) -> bool:
+    """Compare sampled output rows of a device image with the oracle run on
+    the input rows around them (copied back from the device)."""
+    import oracle
+    from synth import unpack_rows
+    ok = True
+    dt = np.uint64 if word_bits == 64 else np.uint32
+    for r in rows:
+        lo, hi = max(0, r - 1), min(height, r + 2)
+        win = unpack_rows(inp[lo:hi].cpu().numpy().view(dt), width)
+        want = oracle.edge_rows(win, lo, [r], height)[0]
+        got = unpack_rows(out[r:r + 1].cpu().numpy().view(dt), width)[0]
+        ok &= bool(np.array_equal(got, want))
+    return ok
+
+
+def rotation_time_ms(torch, tm, fns, min_launches: int, reps: int) -> float:
+    """Per-launch time of launches replayed from one graph on one stream;
+    the list is repeated until the graph holds at least min_launches."""
+    seq = fns * max(1, -(-min_launches // len(fns)))
+    g = graph_of(torch, None, nstreams=1, fns=seq)
+    g.replay()
+    torch.cuda.synchronize()
+    ms = tm.per_call_ms(lambda i: g.replay(), reps) / len(seq)
+    del g
+    return ms
+
+
+def size_sweep(torch, em, tm, sides=(1024, 2048, 4096, 8192, 16384, 32768, 65536)):
+    """Plain method on square uint64 images of fair random bits, sides 2^10
+    .. 2^16, rotating over buffer pairs until at least 640 MiB are touched
+    per round (so every launch reads HBM): per-launch time, Gpx/s, GB/s and
+    the plain copy of the same bytes. Section 6 claims time at most linear in
+    the image size; the fixed launch cost dominates below about 8192^2."""
+    res = []
+    for side in sides:
+        img_bytes = side * side // 8
+        nb = int(min(40, max(1, -(-(640 << 20) // (2 * img_bytes)))))
+        src = random_words(torch, side)
+        ins = [src] + [src.clone() for _ in range(nb - 1)]
+        outs = [torch.empty_like(src) for _ in range(nb)]
+        em.edge_image(ins[0], outs[0], side, side, cfg="tuned")
+        torch.cuda.synchronize()
+        ok = sample_check(ins[0], outs[0], side, side, (0, 1, side // 2, side - 2, side - 1))
+        fns = [(lambda i=i: em.edge_image(ins[i], outs[i], side, side, cfg="tuned"))
+               for i in range(nb)]
+        ms = rotation_time_ms(torch, tm, fns, 40 if side <= 16384 else 4,
+                              5 if side <= 16384 else 3)
+        del ins, outs, src
+        torch.cuda.empty_cache()
+        copy = copy_ceiling(torch, em, tm, img_bytes, nb, 40 if side <= 16384 else 4)
+        gbs = 2 * img_bytes / (ms * 1e-3) / 1e9
+        res.append({"side": side, "us_per_launch": round(ms * 1e3, 2),
+                    "gpx_s": round(side * side / (ms * 1e-3) / 1e9, 1), "gbs": round(gbs, 1),
+                    "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                    "copy_gbs_same_bytes": round(copy, 1),
+                    "frac_of_copy": round(gbs / copy, 3), "buffer_pairs": nb,
+                    "sampled_rows_bit_exact": ok})
+        log(f"sweep {side}^2: {ms * 1e3:.2f} us, {gbs:.0f} GB/s, copy {copy:.0f} GB/s, ok={ok}")
+    return {"workload": "plain, square uint64 images of fair random bits, sides 2^10..2^16, "
+                        "white border, graph-replayed launches over rotating buffer pairs",
+            "sizes": res}
+
+
+def content_independence(torch, em, tm):
+    """Plain-method launch time at 8192^2 (40 rotating pairs) and 65536^2
+    for all-white, all-black, fair random and glyph-stroke images (section 7
+    reports equal times for equally sized images of different content)."""
+    from synth import images, pack_rows
+    res = {}
+    for side, nb in ((8192, 40), (65536, 1)):
+        if side == 8192:
+            strokes = words_tensor(torch, pack_rows(images.glyph_page(8192, 8192, seed=2), 64))
+        else:
+            tile = pack_rows(images.glyph_page(8192, 8192, seed=22), 64)
+            strokes = torch.from_numpy(tile.view(np.int64)).cuda().repeat(8, 8)
+        contents = {"white": lambda t: t.fill_(-1), "black": lambda t: t.zero_(),
+                    "random": lambda t: t.copy_(random_words(torch, side)),
+                    "strokes": lambda t: t.copy_(strokes)}
+        per = {}
+        for name, fill in contents.items():
+            ins = [torch.empty_like(strokes) for _ in range(nb)]
+            for t in ins:
+                fill(t)
+            outs = [torch.empty_like(strokes) for _ in range(nb)]
+            em.edge_image(ins[0], outs[0], side, side, cfg="tuned")
+            torch.cuda.synchronize()
+            o = outs[0]
+            if name == "white":
+                ok = bool((o == 0).all())
+            elif name == "black":   # white border: exactly the frame is edge
+                ok = bool((o[0] == -1).all() and (o[-1] == -1).all()
+                          and (o[1:-1, 0] == 1).all() and (o[1:-1, -1] == (-1 << 63)).all()
+                          and (o[1:-1, 1:-1] == 0).all()) if side >= 128 else None
+            else:
+                ok = sample_check(ins[0], o, side, side, (0, side // 3, side - 1))
+            fns = [(lambda i=i: em.edge_image(ins[i], outs[i], side, side, cfg="tuned"))
+                   for i in range(nb)]
+            ms = rotation_time_ms(torch, tm, fns, 40 if side <= 8192 else 10, 5)
+            per[name] = {"us_per_launch": round(ms * 1e3, 2), "bit_exact": ok}
+            log(f"content {side}^2 {name}: {ms * 1e3:.2f} us ok={ok}")
+            del ins, outs
+            torch.cuda.empty_cache()
+        t = [v["us_per_launch"] for v in per.values()]
+        res[f"{side}"] = dict(per, spread=round((max(t) - min(t)) / min(t), 4))
+        del strokes
+        torch.cuda.empty_cache()
+    return dict(workload="plain, uint64, white border: all-white, all-black, fair random and "
+                         "glyph-stroke images of one size; spread = (max - min) / min time",
+                **res)
+
+
+def host_cores() -> int:
+    """Threads the CPU baseline may use: the cores this process may run on,
+    at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def oracle_banded(img, threads: int, clauses: int = 1):
+    """The oracle on row bands of img, one band per thread (the oracle's C
+    call releases the interpreter lock). Each band is computed with one halo
+    row above and below from the image, so its rows see exactly their
+    neighbours in the whole image; the oracle itself is unchanged."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    H = img.shape[0]
+    cuts = np.linspace(0, H, threads + 1).astype(int)
+    out = np.empty_like(img)
+
+    def band(k):
+        lo, hi = cuts[k], cuts[k + 1]
+        if hi <= lo:
+            return
+        a, b = max(0, lo - 1), min(H, hi + 1)
+        e = oracle.edge(img[a:b], clauses=clauses)
+        out[lo:hi] = e[lo - a:lo - a + (hi - lo)]
+
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(band, range(threads)))
+    return out
+
+
+def cpu_oracle_configs(img8192, budget_s: float = 4.0):
+    """The oracle at each workload size, on one thread and on all host cores
+    (bands of rows in threads), packing excluded; bounded repetitions."""
+    import oracle
+    from synth import images
+    threads = host_cores()
+
+    def rate(fn, px, budget):
+        t0, reps = time.perf_counter(), 0
+        while True:
+            fn()
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= budget or reps >= 50:
+                return px * reps / el / 1e9
+
+    if img8192 is None:
+        img8192 = images.glyph_page(8192, 8192, seed=2)
+    res = {"cores_all": threads, "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    img512, _ = images.strokes_image(512, 512, seed=1)
+    crops = images.glyph_crops(4096, seed=3)
+    page16k = images.skeleton_page(16384, 16384, seed=4)
+    big = np.tile(images.glyph_page(8192, 8192, seed=22), (8, 8))
+    cases = (("plain_512", img512, 1, budget_s / 4), ("plain_8192", img8192, 1, budget_s),
+             ("full_16384", page16k, 3, budget_s), ("plain_65536", big, 1, 0.0))
+    for name, im, cl, bud in cases:
+        one = rate(lambda: oracle.edge(im, clauses=cl), im.size, bud)
+        allc = rate(lambda: oracle_banded(im, threads, cl), im.size, bud)
+        res[name] = {"gpx_s_1_thread": round(one, 4), "gpx_s_all_cores": round(allc, 4)}
+        log(f"cpu oracle {name}: {one:.3f} Gpx/s on 1 thread, {allc:.3f} on {threads}")
+    del big
+    px = int(sum(c.size for c in crops))
+
+    def crops_all():
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(oracle.edge, crops))
+
+    res["batched_4096"] = {"gpx_s_1_thread": round(rate(lambda: [oracle.edge(c) for c in crops],
+                                                        px, budget_s / 2), 4),
+                           "gpx_s_all_cores": round(rate(crops_all, px, budget_s / 2), 4)}
+    return res
+
+
 def cpu_baseline(img, seconds):
     import oracle
     t0 = time.perf_counter()
@@ -529,7 +741,33 @@ def cpu_baseline(img, seconds):
     gpx = img.size * reps / el / 1e9
     return {"value": round(gpx, 4), "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
             "sample": f"{reps} x the 8192x8192 headline image as bytes (packing excluded), "
-                      f"{el:.1f} s on one thread of {platform.processor() or 'the host'}"}
+                      f"{el:.1f} s on one thread of {cpu_model()}"}
+
+
+SECTIONS = {
+    "plain_512": lambda torch, em, tm, a: plain_512(torch, em, tm, a.steps),
+    "plain_65536": lambda torch, em, tm, a: plain_65536(torch, em, tm, 20),
+    "full_16384": lambda torch, em, tm, a: full_16384(torch, em, tm, 50),
+    "batched_4096": lambda torch, em, tm, a: batched_crops(torch, em, tm, a.steps),
+    "next_rows": lambda torch, em, tm, a: next_rows(torch, em, tm, a.steps),
+    "size_sweep": lambda torch, em, tm, a: size_sweep(torch, em, tm),
+    "content": lambda torch, em, tm, a: content_independence(torch, em, tm),
+    "serving": lambda torch, em, tm, a: serving(torch, em),
+    "cpu_configs": lambda torch, em, tm, a: cpu_oracle_configs(None),
+    # the plain copy of 8 MiB or 512 MiB: the reference reading that scales
+    # hardware counters of the edge kernels in the same profiled run
+    "copy_8MiB": lambda torch, em, tm, a: round(copy_ceiling(torch, em, tm, 8 << 20, 40, 40), 1),
+    "copy_512MiB": lambda torch, em, tm, a: round(copy_ceiling(torch, em, tm, 512 << 20, 2, 4),
+                                                  1),
+}
+
+
+def versions(torch) -> dict:
+    p = torch.cuda.get_device_properties(0)
+    return {"torch": torch.__version__, "hip": torch.version.hip, "device": p.name,
+            "arch": getattr(p, "gcnArchName", "?"), "compute_units": p.multi_processor_count,
+            "hbm_gib": round(p.total_memory / 2**30, 1),
+            "clock_mhz": getattr(p, "clock_rate", 0) // 1000 or None}
 
 
 def main():
@@ -544,17 +782,17 @@ def main():
         log("no GPU visible")
         sys.exit(1)
     tm = Timer(torch)
-    if args.serve_only:
-        print(json.dumps(serving(torch, em)), flush=True)
-        return
-    if args.batch_only:
-        print(json.dumps(batched_crops(torch, em, tm, args.steps)), flush=True)
-        return
-    if args.next_only:
-        print(json.dumps(next_rows(torch, em, tm, args.steps)), flush=True)
+    only = args.only or (["serving"] if args.serve_only else ["batched_4096"] if args.batch_only
+                         else ["next_rows"] if args.next_only else None)
+    if only is not None:
+        bad = [k for k in only if k not in SECTIONS]
+        if bad:
+            log(f"unknown section(s) {bad}; known: {list(SECTIONS)}")
+            sys.exit(2)
+        print(json.dumps({k: SECTIONS[k](torch, em, tm, args) for k in only}), flush=True)
         return
     counts = tuple(sorted({1} | {int(v) for v in args.streams.split(",")}))
-    img, per_streams, eager_ms, timed, exact, hcfg = headline(torch, em, tm, args.steps,
+    img, per_streams, eager_ms, timed, exact, hcfg, trials = headline(torch, em, tm, args.steps,
                                                               args.warmup, counts)
     # value and roofline both come from the one-stream graph, where launches
     # do not overlap, so per-step time is the kernel's own duration (the
@@ -582,6 +820,12 @@ def main():
            "bit_exact": exact,
            "eager_python_loop": {"ms_per_step": round(eager_ms, 5),
                                  "gpx_s": round(H * W / (eager_ms * 1e-3) / 1e9, 1)},
+           "trials_one_stream": {"n": len(trials),
+                                 "median_ms": round(float(np.median(trials)), 5),
+                                 "p90_ms": round(float(np.percentile(trials, 90)), 5),
+                                 "min_ms": round(min(trials), 5),
+                                 "max_ms": round(max(trials), 5)},
+           "versions": versions(torch),
            "graph_streams": {str(k): {"ms_per_step": round(v, 5),
                                       "gpx_s": round(H * W / (v * 1e-3) / 1e9, 1)}
                              for k, v in per_streams.items()}}
@@ -595,18 +839,12 @@ def main():
     if not args.headline_only:
         extra = {}
         extra["copy_ceiling_gbs_1GiB"] = round(copy_ceiling(torch, em, tm, 512 << 20, 2, 20), 1)
-        log("config: plain 512^2")
-        extra["plain_512"] = plain_512(torch, em, tm, args.steps)
-        log("config: plain 65536^2")
-        extra["plain_65536"] = plain_65536(torch, em, tm, 20)
-        log("config: full 16384^2")
-        extra["full_16384"] = full_16384(torch, em, tm, 50)
-        log("config: batched crops")
-        extra["batched_4096"] = batched_crops(torch, em, tm, args.steps)
-        log("config: next rows (staged ablation, direction planes, threshold)")
-        extra["next_rows"] = next_rows(torch, em, tm, args.steps)
-        log("config: serving")
-        extra["serving"] = serving(torch, em)
+        for name, fn in SECTIONS.items():
+            if name.startswith("copy_") or (name == "cpu_configs" and args.no_cpu):
+                continue
+            log(f"section: {name}")
+            extra[name] = cpu_oracle_configs(img) if name == "cpu_configs" else \
+                fn(torch, em, tm, args)
         res["extra"] = extra
     print(json.dumps(res), flush=True)
 

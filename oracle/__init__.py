@@ -11,7 +11,9 @@ compiler and marshals numpy arrays to it.
 Parity status: every function here is pinned by the CPU tests in
 ``tests/test_oracle_pins.py`` (Fig. 1 and Fig. 2 fixtures, textbook
 morphology, the paper's literal three-stage construction, exhaustive tiny
-images, closed forms and invariants).
+images, closed forms and invariants) and ``tests/test_oracle_pins_next.py``
+(direction planes, threshold, peeling against the taxicab distance
+transform and iterated textbook erosion).
 """
 from __future__ import annotations
 
@@ -61,6 +63,9 @@ def _load():
     lib.oracle_threshold.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_int64, ctypes.c_int]
     lib.oracle_threshold.restype = ctypes.c_int
+    lib.oracle_peel.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.oracle_peel.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -135,6 +140,23 @@ def threshold(grey: np.ndarray, t: int) -> np.ndarray:
     rc = _load().oracle_threshold(g.ctypes.data, out.ctypes.data, H, W, int(t))
     if rc != 0:
         raise ValueError(f"oracle_threshold rejected its arguments ({rc})")
+    return out
+
+
+def peel(img: np.ndarray, iterations: int, border: str = "white",
+         edge_out: bool = False) -> np.ndarray:
+    """The (H, W) byte image after `iterations` peels (each peel turns the
+    current edge points white), or with ``edge_out`` the edge map of that
+    image. uint8, 1 = white (image) or 1 = edge (edge map)."""
+    a = _as_bytes(img)
+    if a.ndim != 2:
+        raise ValueError("expected a 2-D image")
+    H, W = a.shape
+    out = np.empty((H, W), dtype=np.uint8)
+    rc = _load().oracle_peel(a.ctypes.data, out.ctypes.data, H, W, _BORDER_PIXEL[border],
+                             int(iterations), int(bool(edge_out)))
+    if rc != 0:
+        raise ValueError(f"oracle_peel rejected its arguments ({rc})")
     return out
 
 

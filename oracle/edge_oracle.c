@@ -33,6 +33,7 @@
  */
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 
 #define ORACLE_CLAUSE1 1
 #define ORACLE_CLAUSE2 2
@@ -127,6 +128,40 @@ int oracle_threshold(const uint8_t* grey, uint8_t* out, int64_t H, int64_t W, in
     if (H < 0 || W < 0 || threshold < 0 || threshold > 256) return -1;
     if (H * W > 0 && (grey == NULL || out == NULL)) return -1;
     for (int64_t i = 0; i < H * W; ++i) out[i] = (uint8_t)(grey[i] >= threshold ? 1 : 0);
+    return 0;
+}
+
+/* Iterated peeling of the edge, the step that thinning repeats (section 1
+ * names edge detection as part of thinning): `iterations` times, find the
+ * edge points of the current image (clause 1, the Boolean function Edge(p))
+ * and make them white. Pixels outside the image keep the border colour at
+ * every step. out receives the image after the last peel or, with
+ * `edge_out` set, the edge map of that image (the next layer to be peeled).
+ * Returns 0, or -1 on bad arguments or when scratch memory is unavailable. */
+int oracle_peel(const uint8_t* img, uint8_t* out, int64_t H, int64_t W, int border_pixel,
+                int iterations, int edge_out) {
+    if (H < 0 || W < 0 || iterations < 0) return -1;
+    if (border_pixel != 0 && border_pixel != 1) return -1;
+    if (H * W == 0) return 0;
+    if (img == NULL || out == NULL) return -1;
+    uint8_t* cur = (uint8_t*)malloc((size_t)(H * W));
+    uint8_t* edge = (uint8_t*)malloc((size_t)(H * W));
+    if (cur == NULL || edge == NULL) {
+        free(cur);
+        free(edge);
+        return -1;
+    }
+    for (int64_t i = 0; i < H * W; ++i) cur[i] = img[i] != 0;
+    for (int t = 0; t < iterations; ++t) {
+        oracle_edge_image(cur, edge, H, W, border_pixel, ORACLE_CLAUSE1, 0);
+        for (int64_t i = 0; i < H * W; ++i)
+            if (edge[i]) cur[i] = 1;          /* an edge point is peeled: it turns white */
+    }
+    if (edge_out) oracle_edge_image(cur, out, H, W, border_pixel, ORACLE_CLAUSE1, 0);
+    else
+        for (int64_t i = 0; i < H * W; ++i) out[i] = cur[i];
+    free(cur);
+    free(edge);
     return 0;
 }
 

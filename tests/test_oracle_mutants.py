@@ -34,6 +34,12 @@ MUTANTS = {
     "plane_no_mask": ("const int mask = 1 - pixel(", "const int mask = 1 | pixel("),
     "threshold_strict": ("grey[i] >= threshold ? 1 : 0", "grey[i] > threshold ? 1 : 0"),
     "threshold_inverted": ("grey[i] >= threshold ? 1 : 0", "grey[i] >= threshold ? 0 : 1"),
+    "peel_once_only": ("for (int t = 0; t < iterations; ++t)",
+                       "for (int t = 0; t < (iterations > 0); ++t)"),
+    "peel_one_extra": ("for (int t = 0; t < iterations; ++t)",
+                       "for (int t = 0; t <= iterations; ++t)"),
+    "peel_to_black": ("if (edge[i]) cur[i] = 1;", "if (edge[i]) cur[i] = 0;"),
+    "peel_layer_of_input": ("oracle_edge_image(cur, out,", "oracle_edge_image(img, out,"),
 }
 
 
@@ -46,6 +52,9 @@ def _pin_suite(golden_dir):
         lambda: [nxt.test_planes_match_shifted_ands_and_or_to_edge(s, b)
                  for s in [(17, 33)] for b in pins.BORDERS],
         lambda: nxt.test_threshold_by_histogram_and_bounds(),
+        lambda: nxt.test_peel_rectangle_closed_form(),
+        lambda: [nxt.test_peel_by_taxicab_distance(s, b, q) for s in [(9, 9), (24, 37)]
+                 for b in pins.BORDERS for q in (0.5, 0.9)],
         lambda: pins.test_fig1_four_neighbours_are_2_4_6_8(golden_dir),
         lambda: pins.test_fig2_patterns_are_edge_points(golden_dir),
         lambda: pins.test_fig2_patterns_cover_every_edge_point(golden_dir),
@@ -77,7 +86,7 @@ def test_mutant_is_caught(name, tmp_path, monkeypatch, golden_dir):
     lib = ctypes.CDLL(str(so))
     real = oracle._load()
     for fn in ("oracle_edge_image", "oracle_edge_stack", "oracle_fundamental_edges",
-               "oracle_threshold"):
+               "oracle_threshold", "oracle_peel"):
         getattr(lib, fn).argtypes = getattr(real, fn).argtypes
         getattr(lib, fn).restype = ctypes.c_int
     monkeypatch.setattr(oracle, "_lib", lib)

@@ -101,3 +101,89 @@ def test_threshold_by_histogram_and_bounds():
     assert oracle.threshold(grey, 0).all() and not oracle.threshold(grey, 256).any()
     with pytest.raises(ValueError):
         oracle.threshold(grey, 257)
+
+
+# ---------------------------------------------------------------- peeling --
+# One peel turns the current edge points white. A black pixel is an edge
+# point exactly when a 4-neighbour is white, so after k peels a black pixel
+# is left exactly when no white pixel (or white outside, under the white
+# border) lies within taxicab distance k of it. On a rectangular grid the
+# taxicab distance inside the image equals the distance in the plane, so the
+# black-border case needs no path argument either.
+
+CROSS = np.array([[0, 1, 0], [1, 1, 1], [0, 1, 0]], bool)
+
+
+def taxicab_to_white(img, border):
+    """Taxicab distance from each pixel to the nearest white pixel (0 on
+    white pixels), from scipy's exact city-block distance transform; a
+    white border adds a white frame around the image. None when no white
+    pixel exists at all."""
+    from scipy import ndimage
+    black = np.asarray(img) == 0
+    if border == "white":
+        black = np.pad(black, 1, constant_values=False)
+    if black.all():
+        return None
+    d = ndimage.distance_transform_cdt(black, metric="taxicab")
+    return d[1:-1, 1:-1] if border == "white" else d
+
+
+@pytest.mark.parametrize("border", BORDERS)
+@pytest.mark.parametrize("shape", [(1, 1), (1, 13), (13, 1), (9, 9), (24, 37), (40, 33)])
+@pytest.mark.parametrize("q", [0.15, 0.5, 0.9])
+def test_peel_by_taxicab_distance(shape, border, q):
+    rng = np.random.default_rng(int(q * 100) + shape[0] * 97 + shape[1])
+    img = (rng.random(shape) >= q).astype(np.uint8)      # q = black fraction
+    d = taxicab_to_white(img, border)
+    for k in range(0, 7):
+        got = oracle.peel(img, k, border=border)
+        lay = oracle.peel(img, k, border=border, edge_out=True)
+        if d is None:       # all black under a black border: nothing ever peels
+            assert not got.any() and not lay.any()
+            continue
+        np.testing.assert_array_equal(got, (d <= k).astype(np.uint8), err_msg=f"k={k}")
+        np.testing.assert_array_equal(lay, (d == k + 1).astype(np.uint8), err_msg=f"k={k}")
+
+
+@pytest.mark.parametrize("border", BORDERS)
+def test_peel_equals_iterated_textbook_erosion(border):
+    """k peels = k erosions of the black set by the 4-connected cross with
+    the outside held at the border colour (scipy, one call per k)."""
+    from scipy import ndimage
+    rng = np.random.default_rng(12)
+    img = (rng.random((31, 45)) >= 0.8).astype(np.uint8)
+    black = img == 0
+    for k in range(1, 6):
+        er = ndimage.binary_erosion(black, structure=CROSS, iterations=k,
+                                    border_value=0 if border == "white" else 1)
+        np.testing.assert_array_equal(oracle.peel(img, k, border=border), (~er).astype(np.uint8))
+
+
+def test_peel_rectangle_closed_form():
+    """A filled w x h black rectangle on white shrinks by one pixel on every
+    side per peel: (w - 2k)(h - 2k) pixels are left while both are positive,
+    and the k-th layer holds the rest of the (w - 2k + 2)(h - 2k + 2) ring."""
+    for (w, h) in [(1, 1), (2, 5), (7, 7), (11, 6), (20, 3)]:
+        img = np.ones((h + 6, w + 6), np.uint8)
+        img[3:3 + h, 3:3 + w] = 0
+        for k in range(0, max(w, h) + 2):
+            left = max(0, w - 2 * k) * max(0, h - 2 * k)
+            assert int((oracle.peel(img, k) == 0).sum()) == left, (w, h, k)
+
+
+def test_peel_zero_steps_and_layers():
+    rng = np.random.default_rng(3)
+    img = (rng.random((19, 27)) >= 0.7).astype(np.uint8)
+    for border in BORDERS:
+        np.testing.assert_array_equal(oracle.peel(img, 0, border=border), img)
+        np.testing.assert_array_equal(oracle.peel(img, 0, border=border, edge_out=True),
+                                      oracle.edge(img, border=border))
+        for k in range(0, 5):   # the edge of the k-times peeled image is the (k+1)-th peel
+            a, b = oracle.peel(img, k, border=border), oracle.peel(img, k + 1, border=border)
+            np.testing.assert_array_equal(oracle.peel(img, k, border=border, edge_out=True),
+                                          b & (1 - a))
+            np.testing.assert_array_equal(oracle.peel(a, 2, border=border),
+                                          oracle.peel(img, k + 2, border=border))
+    with pytest.raises(ValueError):
+        oracle.peel(img, -1)
