@@ -521,6 +521,56 @@ def next_rows(torch, em, tm, steps):
     return res
 
 
+def peel_section(torch, em, tm, ks=(1, 2, 4, 8, 16, 30)):
+    """Iterated peeling of the 8192^2 glyph page (uint64): k peels in one
+    fused pass against k launches of a single peel (ping-pong buffers);
+    sampled rows checked against the oracle, the fused result against the
+    repeated one on the whole image."""
+    from synth import images, pack_rows, unpack_rows
+    import oracle
+    H = W = 8192
+    img = images.glyph_page(H, W, seed=2)
+    src = words_tensor(torch, pack_rows(img, 64))
+    NB = 10
+    ins = [src] + [src.clone() for _ in range(NB - 1)]
+    outs = [torch.empty_like(src) for _ in range(NB)]
+    tmp = [torch.empty_like(src) for _ in range(2)]
+    nbytes = 2 * H * (W // 64) * 8
+    rows = [0, 1, 4095, 8190, 8191]
+    res = {"workload": "iterated peeling of the 8192x8192 glyph page (seed 2), uint64, white "
+                       "border, 10 rotating buffer pairs; fused = one edge_peel call of k peels",
+           "runs": []}
+    for k in ks:
+        fns = [(lambda i=i: em.peel(ins[i], outs[i], H, W, k)) for i in range(NB)]
+        ms = rotation_time_ms(torch, tm, fns, 20, 5)
+
+        def repeated(i=0):
+            a = ins[i]
+            for s_ in range(k):
+                em.peel(a, tmp[s_ % 2], H, W, 1)
+                a = tmp[s_ % 2]
+            return a
+
+        ms_rep = rotation_time_ms(torch, tm, [lambda: repeated()], 5, 3)
+        em.peel(ins[0], outs[0], H, W, k)
+        last = repeated()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(outs[0], last))
+        got = unpack_rows(outs[0][rows].cpu().numpy().view(np.uint64), W)
+        want = np.stack([oracle.peel(img[max(0, y - k - 2):min(H, y + k + 3)], k)
+                         [y - max(0, y - k - 2)] for y in rows])
+        ok = bool(np.array_equal(got, want)) and same
+        res["runs"].append({"k": k, "us_fused": round(ms * 1e3, 2), "us_repeated": round(ms_rep * 1e3, 2),
+                            "speedup": round(ms_rep / ms, 2),
+                            "gbs_fused": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                            "gpx_peels_s": round(H * W * k / (ms * 1e-3) / 1e9, 1),
+                            "bit_exact": ok})
+        log(f"peel k={k}: fused {ms * 1e3:.2f} us, repeated {ms_rep * 1e3:.2f} us, ok={ok}")
+    del ins, outs, tmp, src
+    torch.cuda.empty_cache()
+    return res
+
+
 def random_words(torch, side: int):
     """A side x side image of independent fair random bits (Bernoulli(0.5)),
     packed uint64, drawn on the device."""
@@ -752,6 +802,7 @@ SECTIONS = {
     "next_rows": lambda torch, em, tm, a: next_rows(torch, em, tm, a.steps),
     "size_sweep": lambda torch, em, tm, a: size_sweep(torch, em, tm),
     "content": lambda torch, em, tm, a: content_independence(torch, em, tm),
+    "peel": lambda torch, em, tm, a: peel_section(torch, em, tm),
     "serving": lambda torch, em, tm, a: serving(torch, em),
     "cpu_configs": lambda torch, em, tm, a: cpu_oracle_configs(None),
     # the plain copy of 8 MiB or 512 MiB: the reference reading that scales

@@ -89,9 +89,13 @@ enum { EDGE_MODE_MASKS = 0, EDGE_MODE_FULL = 1 };
  * polarity of section 5 (edge pixels 0, others 1); padding bits stay 0.
  * PLANNED (batch calls only): the workspace already holds the plan that
  * edge_batch_plan made for this table, arenas, word size and cfg, so the
- * device planner is skipped. */
+ * device planner is skipped. PEEL_EDGE (edge_peel only): output the edge
+ * map of the peeled image. */
 enum { EDGE_FLAG_CLAUSE2_ONLY = 1u << 0, EDGE_FLAG_INVERT_OUT = 1u << 1,
-       EDGE_FLAG_PLANNED = 1u << 2 };
+       EDGE_FLAG_PLANNED = 1u << 2, EDGE_FLAG_PEEL_EDGE = 1u << 3 };
+
+/* Most peels edge_peel does in one call. */
+#define EDGE_PEEL_MAX_ITERATIONS 30
 
 /* One image of a batch. Offsets and strides count B-bit words from the
  * start of the arena; in and out arenas share the same descriptors. */
@@ -186,6 +190,21 @@ int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int thresh
 int edge_masks_staged(const void* in, void* out, void* scratch, int64_t scratch_bytes,
                       int64_t height, int64_t width, int64_t stride_words, int word_bits,
                       int border, void* hip_stream);
+
+/* Iterated peeling of the edge: `iterations` times, every edge point of
+ * the current image (Edge(p) of section 1) turns white, pixels outside the
+ * image keeping the border colour; thinning repeats this step (section 1).
+ * A black pixel is left after k peels exactly when no white pixel (nor,
+ * under the white border, the outside) lies within taxicab distance k of it.
+ * out receives the peeled image, or with EDGE_FLAG_PEEL_EDGE its edge map
+ * (the pixels the next peel would remove; iterations = 0 then gives the
+ * output of edge_masks). Layout, padding and alias rules as edge_masks;
+ * 0 <= iterations <= EDGE_PEEL_MAX_ITERATIONS, all done in one pass over
+ * the image. cfg: NULL, or a configuration whose rows_per_tile and
+ * waves_per_block are used (loads always go through the caches). */
+int edge_peel(const void* in, void* out, int64_t height, int64_t width, int64_t stride_words,
+              int word_bits, int border, int iterations, uint32_t flags,
+              const edge_launch_cfg* cfg, void* hip_stream);
 
 /* Built-in launch configuration for an image shape (batch != 0: for the
  * persistent batch kernel). Returns EDGE_OK and fills *cfg_out. */

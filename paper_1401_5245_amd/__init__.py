@@ -16,8 +16,8 @@ import ctypes
 import torch
 
 from ._abi import (EDGE_BORDER_BLACK, EDGE_BORDER_WHITE, EDGE_FLAG_CLAUSE2_ONLY,  # noqa: F401
-                   EDGE_FLAG_INVERT_OUT, EDGE_MODE_FULL, EDGE_MODE_MASKS, EdgeError,
-                   EdgeImageDesc, EdgeLaunchCfg, check, load)
+                   EDGE_FLAG_INVERT_OUT, EDGE_FLAG_PEEL_EDGE, EDGE_MODE_FULL, EDGE_MODE_MASKS,
+                   EDGE_PEEL_MAX_ITERATIONS, EdgeError, EdgeImageDesc, EdgeLaunchCfg, check, load)
 
 _lib = load()
 
@@ -159,6 +159,20 @@ def threshold_edges(grey: torch.Tensor, out: torch.Tensor, height: int, width: i
     check(_lib.edge_threshold_edges(grey.data_ptr(), gs, int(threshold), out.data_ptr(), height,
                                     width, s, wb, BORDERS[border], MODES[mode], flags,
                                     _cfg_ptr(c), stream_handle(stream)))
+    return out
+
+
+def peel(inp: torch.Tensor, out: torch.Tensor, height: int, width: int, iterations: int, *,
+         border: str = "white", edge_out: bool = False, cfg=None, stride_words=None,
+         stream=None) -> torch.Tensor:
+    """`iterations` peels of the edge in one pass (each turns the current
+    edge points white; at most EDGE_PEEL_MAX_ITERATIONS). With ``edge_out``
+    the output is the edge map of the peeled image (the next layer)."""
+    wb, s = _image_args(inp, out, height, width, stride_words)
+    c = None if cfg is None else (EdgeLaunchCfg.from_dict(cfg) if isinstance(cfg, dict) else cfg)
+    check(_lib.edge_peel(inp.data_ptr(), out.data_ptr(), height, width, s, wb, BORDERS[border],
+                         int(iterations), EDGE_FLAG_PEEL_EDGE if edge_out else 0, _cfg_ptr(c),
+                         stream_handle(stream)))
     return out
 
 

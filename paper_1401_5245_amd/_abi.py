@@ -26,6 +26,8 @@ EDGE_MODE_FULL = 1
 EDGE_FLAG_CLAUSE2_ONLY = 1 << 0
 EDGE_FLAG_INVERT_OUT = 1 << 1
 EDGE_FLAG_PLANNED = 1 << 2
+EDGE_FLAG_PEEL_EDGE = 1 << 3
+EDGE_PEEL_MAX_ITERATIONS = 30
 
 c_i32, c_i64, c_u32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p
 
@@ -76,6 +78,8 @@ _SIGNATURES = {
     "edge_threshold_edges": (ctypes.c_int, [c_vp, c_i64, ctypes.c_int, c_vp, c_i64, c_i64, c_i64,
                                             ctypes.c_int, ctypes.c_int, ctypes.c_int, c_u32,
                                             ctypes.POINTER(EdgeLaunchCfg), c_vp]),
+    "edge_peel": (ctypes.c_int, [c_vp, c_vp, c_i64, c_i64, c_i64, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int, c_u32, ctypes.POINTER(EdgeLaunchCfg), c_vp]),
     "edge_masks_staged": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_i64,
                                          ctypes.c_int, ctypes.c_int, c_vp]),
     "edge_default_cfg": (ctypes.c_int, [c_i64, c_i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,

@@ -119,6 +119,14 @@ __device__ __forceinline__ uint32_t from_upper_lane(uint32_t v, uint32_t fill) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x130, 0xf, 0xf, false);
 }
 
+// The same shifts with 0 shifted in (bound_ctrl), one instruction each.
+__device__ __forceinline__ uint32_t from_lower_lane0(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xf, 0xf, true);
+}
+__device__ __forceinline__ uint32_t from_upper_lane0(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xf, 0xf, true);
+}
+
 // Second clause of the definition in section 1, bit-sliced over 32 pixels:
 // bit x is 1 when at most one of the eight neighbour words has a 0 (black)
 // at bit x. `none` tracks "no black so far", `one` "at most one so far".
@@ -424,6 +432,107 @@ __device__ __forceinline__ void strip_unit(const Geom& g, int j0, int y0, int y1
         if (edges) strip_body<VW, MODE, false, true, Pol>(g, j0, y0, y1, bw, invert);
         else strip_body<VW, MODE, false, false, Pol>(g, j0, y0, y1, bw, invert);
     }
+}
+
+// ---------------------------------------------------------------- peeling ----
+
+// Iterated peeling of the edge (edge detection as the step that thinning
+// repeats, section 1): one peel turns every edge point white. Since
+// Edge(p) = ~p & (n2 | n4 | n6 | n8), the peeled pixel is p | n2 | n4 | n6 | n8:
+// one level of white dilation by the 4-neighbour cross. A peel unit forms L
+// levels in registers while its wavefront walks down the rows, so L peels
+// cost one read and one write of the image.
+//
+// Lanes: a wavefront covers 64 consecutive 32-bit words of each row, one per
+// lane, and stores lanes 1..62 only (kPeelSpan words per chunk); lanes 0 and
+// 63 hold the words on either side as a halo. Their outer neighbours are
+// never loaded (black is shifted in), so after j levels the bits within j
+// pixels of a halo word's far side may be wrong; with L <= 31 the bit next
+// to the stored span never is.
+//
+// Outside the image: words past the row ends and rows above and below start
+// as border words and are then dilated like the image itself. The region
+// that evolves is a rectangle containing the image, and in a rectangle the
+// shortest 4-connected path between two pixels inside never needs to leave
+// the image, so the stored words equal those of the definition in which
+// outside pixels keep the border colour at every step (white outside stays
+// white in both readings).
+//
+// Level j of row r is L_j(r) = c | W(c) | E(c) | L_{j-1}(r-1) | L_{j-1}(r+1)
+// with c = L_{j-1}(r) and W, E its one-pixel shifts (carries from the
+// neighbouring lanes by DPP): six VALU operations per word and level. It is
+// formed at the step where level 0 reaches row r + j; each level keeps its
+// two most recent rows. EDGEOUT stores L_L & ~L_{L-1}, the edge map of the
+// image after L - 1 peels; COPY (L = 1 only) stores the input unchanged.
+constexpr int kPeelSpan = kWave - 2;
+
+template <int L, bool EDGEOUT, bool COPY, class Pol>
+__device__ __forceinline__ void peel_unit(const Geom& g, int64_t chunk, int y0, int y1,
+                                          uint32_t bw) {
+    static_assert(L >= 1 && L <= 31, "the halo lanes carry 32 pixels");
+    static_assert(!COPY || (L == 1 && !EDGEOUT), "COPY is the zero-peel case");
+    // three rows in flight: each level's rows rotate through three
+    // registers, so a loop body of three steps needs no register moves
+    constexpr int P = 3;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t j = chunk * kPeelSpan - 1 + lane;      // may lie outside the row
+    const bool inrow = j >= 0 && j < g.wd;
+    const bool keep = inrow && lane >= 1 && lane <= kWave - 2;
+    const uint32_t vm = inrow ? valid_bits((int)j, g.width) : 0u;
+    const uint32_t om = bw & ~vm;                        // outside the row: all border
+    const int64_t jl = inrow ? j : (j < 0 ? 0 : (int64_t)g.wd - 1);
+
+    auto load = [&](int y) -> uint32_t {
+        const int yc = y < 0 ? 0 : (y >= g.height ? g.height - 1 : y);
+        const uint32_t* p = g.in + (int64_t)yc * g.stride + jl;
+        return Pol::nt_load ? __builtin_nontemporal_load(p) : *p;
+    };
+
+    uint32_t A[L], B[L];     // level i: rows t-i-2 and t-i-1 at the start of step t
+#pragma unroll
+    for (int i = 0; i < L; ++i) { A[i] = bw; B[i] = bw; }
+
+    auto step = [&](int t, uint32_t raw) {
+        uint32_t n = (unsigned)t < (unsigned)g.height ? ((raw & vm) | om) : bw;   // L_0(t)
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            // level i + 1 at row t - i - 1 from level i rows t-i-2, t-i-1, t-i
+            const uint32_t c = B[i];
+            uint32_t v = c;
+            if constexpr (!COPY) {
+                const uint32_t lw = from_lower_lane0(c), le = from_upper_lane0(c);
+                v = (c | west_of(c, lw) | east_of(c, le)) | (A[i] | n);
+            }
+            A[i] = c;
+            B[i] = n;
+            n = v;
+        }
+        const int y = t - L;                  // n = L_L(y); A[L-1] = L_{L-1}(y)
+        if (y >= y0 && keep) {
+            const uint32_t res = (EDGEOUT ? (n & ~A[L - 1]) : n) & vm;
+            uint32_t* op = g.out + (int64_t)y * g.stride + j;
+            if constexpr (Pol::nt_store) __builtin_nontemporal_store(res, op);
+            else *op = res;
+        }
+    };
+
+    const int t0 = y0 - L, tlast = y1 - 1 + L;
+    uint32_t q[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) q[u] = load(min(t0 + u, tlast));
+    int t = t0;
+    for (; t + P <= tlast + 1; t += P) {
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const uint32_t w = q[u];
+            q[u] = load(min(t + u + P, tlast));
+            step(t + u, w);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u + 1 < P; ++u)
+        if (t + u <= tlast) step(t + u, q[u]);
 }
 
 // --------------------------------------------------------- narrow units ----

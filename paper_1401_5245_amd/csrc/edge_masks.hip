@@ -52,6 +52,22 @@ __global__ void __launch_bounds__(512) k_strip_grey(Geom g, int64_t chunk0, int6
                                      invert != 0);
 }
 
+// Iterated peeling of one image: strips of `rows` rows x kPeelSpan words,
+// one wavefront per strip, L levels.
+template <int L, bool EDGEOUT, bool COPY, class Pol>
+__global__ void __launch_bounds__(512) k_peel(Geom g, int64_t chunks, int rows, int64_t nunits,
+                                              uint32_t bw) {
+    const int wpb = blockDim.x / kWave;
+    const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
+                         wave_uniform(threadIdx.x / kWave);
+    if (unit >= nunits) return;
+    const int64_t strip = unit / chunks;
+    const int64_t chunk = unit - strip * chunks;
+    const int64_t y0 = strip * rows;
+    const int64_t y1 = y0 + rows < g.height ? y0 + rows : g.height;
+    peel_unit<L, EDGEOUT, COPY, Pol>(g, chunk, (int)y0, (int)y1, bw);
+}
+
 // One image with rows of <= 32 words, `band` rows per wavefront.
 template <int MODE>
 __global__ void __launch_bounds__(512) k_narrow(Geom g, int64_t band, int64_t nunits, uint32_t bw,
@@ -740,6 +756,50 @@ int launch_grey_mode(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int i
 
 namespace {
 
+template <int L, bool EDGEOUT, bool COPY>
+int launch_peel_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, hipStream_t s) {
+    const int64_t chunks = ceil_div(g.wd, (int64_t)kPeelSpan);
+    const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
+    const int64_t blocks = ceil_div(nunits, c.waves_per_block);
+    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL((k_peel<L, EDGEOUT, COPY, CachedStrip>), dim3((uint32_t)blocks),
+                       dim3(c.waves_per_block * kWave), 0, s, g, chunks, c.rows_per_tile, nunits,
+                       bw);
+    return launch_status();
+}
+
+// One instantiation per level count 1..31 (levels are a template constant
+// so that every level's rows stay in registers).
+template <int L, bool EDGEOUT>
+int launch_peel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int levels, hipStream_t s) {
+    if constexpr (L > 31) {
+        return EDGE_ERR_INVALID;
+    } else {
+        if (levels == L) return launch_peel_kernel<L, EDGEOUT, false>(g, c, bw, s);
+        return launch_peel<L + 1, EDGEOUT>(g, c, bw, levels, s);
+    }
+}
+
+// Built-in peel shape, from a sweep at 8192^2 and 16384^2: a unit
+// recomputes 2 * iterations halo rows, so strips are about twice as tall as
+// the iteration count (at least 8, at most 64 rows), doubled once when the
+// image would still give more than 8192 strips; 4 wavefronts per workgroup.
+// cache_policy is not used: peel units load through the caches, which keep
+// the halo rows that neighbouring strips share.
+edge_launch_cfg default_peel(int64_t height, int64_t wd32, int iterations) {
+    edge_launch_cfg c;
+    c.vec_words = 1;
+    c.blocks_per_cu = 1;
+    c.cache_policy = EDGE_CACHE_NORMAL;
+    c.waves_per_block = 4;
+    const int64_t chunks = ceil_div(wd32, (int64_t)kPeelSpan);
+    int64_t rows = 8;
+    while (rows < 2 * iterations && rows < 64) rows *= 2;
+    if (rows < 64 && chunks * ceil_div(height, rows) > 8192) rows *= 2;
+    c.rows_per_tile = (int32_t)rows;
+    return c;
+}
+
 template <int STAGE>
 int launch_stage(const uint32_t* img, const uint32_t* src, uint32_t* dst, int64_t stride,
                  int32_t height, int32_t width, int32_t wd, uint32_t bw, hipStream_t s) {
@@ -895,6 +955,46 @@ int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int thresh
         case kModeFull: return launch_grey_mode<kModeFull>(g, c, bw, inv, vec, s);
         default: return launch_grey_mode<kModeClause2>(g, c, bw, inv, vec, s);
     }
+}
+
+int edge_peel(const void* in, void* out, int64_t height, int64_t width, int64_t stride_words,
+              int word_bits, int border, int iterations, uint32_t flags,
+              const edge_launch_cfg* cfg, void* hip_stream) {
+    if (word_bits != 32 && word_bits != 64) return EDGE_ERR_INVALID;
+    if (border != EDGE_BORDER_WHITE && border != EDGE_BORDER_BLACK) return EDGE_ERR_INVALID;
+    if (flags & ~(uint32_t)EDGE_FLAG_PEEL_EDGE) return EDGE_ERR_INVALID;
+    if (iterations < 0 || iterations > EDGE_PEEL_MAX_ITERATIONS) return EDGE_ERR_INVALID;
+    if (height < 0 || width < 0 || stride_words < 0) return EDGE_ERR_INVALID;
+    if (height > 0x7fffffff || width > 0x7fffffff) return EDGE_ERR_INVALID;
+    if (cfg && !cfg_ok(*cfg)) return EDGE_ERR_INVALID;
+    if (height == 0 || width == 0) return EDGE_OK;
+    if (!in || !out) return EDGE_ERR_INVALID;
+    const int64_t wd = ceil_div(width, word_bits);
+    if (stride_words < wd) return EDGE_ERR_INVALID;
+    const int word_bytes = word_bits / 8;
+    const uintptr_t pin = (uintptr_t)in, pout = (uintptr_t)out;
+    if (pin % word_bytes || pout % word_bytes) return EDGE_ERR_ALIGN;
+    if (stride_words > (int64_t)(INT64_MAX / 8) / height) return EDGE_ERR_INVALID;
+    const uint64_t span = (uint64_t)((height - 1) * stride_words + wd) * word_bytes;
+    if (ranges_overlap(pin, span, pout, span)) return EDGE_ERR_ALIAS;
+    const int per = word_bits / 32;
+    Geom g;
+    g.in = (const uint32_t*)in;
+    g.out = (uint32_t*)out;
+    g.stride = stride_words * per;
+    g.height = (int32_t)height;
+    g.width = (int32_t)width;
+    g.wd = (int32_t)(wd * per);
+    g.plane = 0;
+    g.grey = nullptr;
+    g.grey_stride = 0;
+    g.thr = 0;
+    const edge_launch_cfg c = cfg ? *cfg : default_peel(height, g.wd, iterations);
+    const uint32_t bw = border_word(border);
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (flags & EDGE_FLAG_PEEL_EDGE) return launch_peel<1, true>(g, c, bw, iterations + 1, s);
+    if (iterations == 0) return launch_peel_kernel<1, false, true>(g, c, bw, s);
+    return launch_peel<1, false>(g, c, bw, iterations, s);
 }
 
 int edge_masks_staged(const void* in, void* out, void* scratch, int64_t scratch_bytes,

@@ -251,11 +251,17 @@ def _main(argv=None):
     ap.add_argument("--out", default=DEFAULT_CACHE)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--squares", default="",
+                    help="comma-separated sides of square uint64 plain-method images to tune "
+                         "instead of the default workloads (no batch)")
     a = ap.parse_args(argv)
     cache = TuneCache(a.out)
     rng = np.random.default_rng(a.seed)
-    for (H, W, wb, mode) in ((512, 512, 32, "masks"), (8192, 8192, 64, "masks"),
-                             (16384, 16384, 64, "full"), (65536, 65536, 64, "masks")):
+    shapes = ((512, 512, 32, "masks"), (8192, 8192, 64, "masks"),
+              (16384, 16384, 64, "full"), (65536, 65536, 64, "masks"))
+    if a.squares:
+        shapes = tuple((int(v), int(v), 64, "masks") for v in a.squares.split(","))
+    for (H, W, wb, mode) in shapes:
         words = -(-W // wb) * (wb // 32) * H
         inp = torch.from_numpy(rng.integers(0, 2**31, size=words, dtype=np.int64)
                                .astype(np.int32)).cuda()
@@ -268,6 +274,10 @@ def _main(argv=None):
         print(f"image {H}x{W} B{wb} {mode}: {us:.2f} us  {cfg}", flush=True)
         del inp, out
         torch.cuda.empty_cache()
+    if a.squares:
+        cache.save(a.out)
+        print("wrote", a.out)
+        return
     from synth import images, pack_rows
     crops = images.glyph_crops(4096, seed=3)
     b = em.Batch([(pack_rows(c, 32), c.shape[1]) for c in crops], 32)

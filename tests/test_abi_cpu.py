@@ -83,6 +83,23 @@ def test_mode_flag_and_cfg_validation():
     assert launch(out=A + 4 * 16, H=0) == OK
 
 
+def peel(inp=A, out=B, H=4, W=100, S=4, wb=32, border=0, k=3, flags=0, cfg=None):
+    return lib.edge_peel(inp, out, H, W, S, wb, border, k, flags, cfg, None)
+
+
+@pytest.mark.parametrize("kw,want", [
+    (dict(wb=16), INVALID), (dict(border=2), INVALID), (dict(H=-1), INVALID),
+    (dict(S=3), INVALID), (dict(inp=None), INVALID), (dict(out=None), INVALID),
+    (dict(inp=A + 2), ALIGN), (dict(out=A + 16), ALIAS), (dict(k=-1), INVALID),
+    (dict(k=_abi.EDGE_PEEL_MAX_ITERATIONS + 1), INVALID), (dict(flags=1), INVALID),
+    (dict(flags=_abi.EDGE_FLAG_PEEL_EDGE | _abi.EDGE_FLAG_INVERT_OUT), INVALID),
+    (dict(cfg=ctypes.byref(_abi.EdgeLaunchCfg(4, 0, 4, 1, 0))), INVALID),
+    (dict(H=0), OK), (dict(W=0, inp=None, out=None), OK),
+])
+def test_peel_validation(kw, want):
+    assert peel(**kw) == want
+
+
 def test_default_cfg():
     c = _abi.EdgeLaunchCfg()
     assert lib.edge_default_cfg(8192, 8192, 64, 0, 0, ctypes.byref(c)) == OK

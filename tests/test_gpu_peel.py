@@ -1,0 +1,134 @@
+"""Iterated edge peeling on the GPU (edge_peel), bit-exact against the
+oracle's repeated peel, plus properties that hold at any size."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import images, pack_rows, pad_bits_zero, row_words, unpack_rows
+from tests.gpu_util import SENTINEL32, assert_same, log, to_device_words
+
+pytestmark = pytest.mark.gpu
+
+ITERS = [0, 1, 2, 3, 5, 8, 9, 16, 17, 30]
+# widths around the 62-word chunk of a peel wavefront (32-bit words): 1984
+# pixels fill one chunk exactly, 1985 spill one word into the next
+SHAPES = [(1, 1), (1, 70), (5, 31), (3, 33), (40, 257), (17, 1000), (9, 1984), (12, 1985),
+          (33, 4100), (70, 8193), (130, 64)]
+
+
+def sparse_white(H, W, seed, p=0.004):
+    """Mostly black with scattered white pixels, so deep peels still
+    change the image."""
+    rng = np.random.default_rng(seed)
+    return (rng.random((H, W)) < p).astype(np.uint8)
+
+
+def run_peel(img, word_bits, k, *, border="white", edge_out=False, stride_extra=1, cfg=None):
+    import paper_1401_5245_amd as em
+    H, W = img.shape
+    S = row_words(W, word_bits) + stride_extra
+    words = pack_rows(img, word_bits, S, pad="random", seed=H + 3 * W)
+    inp = to_device_words(words)
+    sent = words.dtype.type(SENTINEL32 if word_bits == 32 else 0xA5A5A5A5A5A5A5A5)
+    out = to_device_words(np.full_like(words, sent))
+    em.peel(inp, out, H, W, k, border=border, edge_out=edge_out, cfg=cfg, stride_words=S)
+    torch.cuda.synchronize()
+    ow = out.cpu().numpy().view(words.dtype).reshape(H, S)
+    assert (ow[:, row_words(W, word_bits):] == sent).all(), "stride padding was written"
+    assert pad_bits_zero(ow, W), "output pad bits are not zero"
+    return unpack_rows(ow, W)
+
+
+@pytest.mark.parametrize("word_bits", [32, 64])
+@pytest.mark.parametrize("H,W", SHAPES)
+def test_peel_matches_oracle(word_bits, H, W):
+    log(f"peel B={word_bits} {H}x{W}")
+    img = sparse_white(H, W, seed=H * 131 + W)
+    for border in ("white", "black"):
+        for k in ITERS:
+            for edge_out in (False, True):
+                got = run_peel(img, word_bits, k, border=border, edge_out=edge_out)
+                want = oracle.peel(img, k, border=border, edge_out=edge_out)
+                assert_same(got, want, f"k={k} edge_out={edge_out} {border}")
+
+
+@pytest.mark.parametrize("cfg", [dict(rows_per_tile=1, waves_per_block=1),
+                                 dict(rows_per_tile=3, waves_per_block=2),
+                                 dict(rows_per_tile=7, waves_per_block=8, cache_policy=2),
+                                 dict(rows_per_tile=64, waves_per_block=4, cache_policy=1),
+                                 dict(rows_per_tile=256, waves_per_block=4)])
+def test_peel_cfgs(cfg):
+    img = images.glyph_page(300, 3000, seed=8, noise=0.02)
+    img = np.where(sparse_white(300, 3000, seed=2, p=0.001) == 1, 1, img).astype(np.uint8)
+    full = dict(vec_words=1, blocks_per_cu=1, cache_policy=0)
+    full.update(cfg)
+    for k in (1, 7, 30):
+        for edge_out in (False, True):
+            got = run_peel(img, 64, k, edge_out=edge_out, cfg=full, stride_extra=0)
+            assert_same(got, oracle.peel(img, k, edge_out=edge_out), f"{cfg} k={k}")
+
+
+def test_peel_zero_is_input_and_edge_is_edge_masks():
+    import paper_1401_5245_amd as em
+    img = images.glyph_page(257, 1111, seed=3, noise=0.01)
+    assert_same(run_peel(img, 32, 0), img, "zero peels")
+    words = pack_rows(img, 32)
+    inp = to_device_words(words)
+    a, b = torch.empty_like(inp), torch.empty_like(inp)
+    em.peel(inp, a, *img.shape, 0, edge_out=True)
+    em.edge_masks(inp, b, *img.shape)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def oracle_rows(img, k, rows, border="white", edge_out=False):
+    """Rows of the oracle's peel of a tall image, each from a window of
+    k + 2 rows on either side: a peel moves information one row, so the
+    window's cut edges cannot reach the middle row."""
+    H = img.shape[0]
+    out = []
+    for y in rows:
+        lo, hi = max(0, y - k - 2), min(H, y + k + 3)
+        out.append(oracle.peel(img[lo:hi], k, border=border, edge_out=edge_out)[y - lo])
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("k", [1, 8, 30])
+def test_peel_8192_sampled_rows(k):
+    """The 8192^2 glyph page in uint64 words, in the built-in launch shape:
+    sampled rows against the oracle on row windows."""
+    import paper_1401_5245_amd as em
+    H = W = 8192
+    log(f"peel 8192^2 k={k}")
+    img = images.glyph_page(H, W, seed=2)
+    inp = to_device_words(pack_rows(img, 64))
+    out = torch.empty_like(inp)
+    rows = [0, 1, 2, 31, 32, 33, 4095, 4096, 8159, 8190, 8191]
+    for edge_out in (False, True):
+        em.peel(inp, out, H, W, k, edge_out=edge_out)
+        torch.cuda.synchronize()
+        got = unpack_rows(out[rows].cpu().numpy().view(np.uint64), W)
+        assert_same(got, oracle_rows(img, k, rows, edge_out=edge_out), f"k={k} {edge_out}")
+
+
+def test_peel_composes():
+    """k peels in one call equal k single peels, and a peels then b peels
+    equal a + b peels (2048^2, random sparse-white content, both borders)."""
+    import paper_1401_5245_amd as em
+    H = W = 2048
+    img = sparse_white(H, W, seed=11, p=0.002)
+    inp = to_device_words(pack_rows(img, 64))
+    for border in ("white", "black"):
+        a, b, c = (torch.empty_like(inp) for _ in range(3))
+        em.peel(inp, a, H, W, 12, border=border)
+        src, dst = inp, b
+        for i in range(12):
+            em.peel(src, dst, H, W, 1, border=border)
+            src, dst = dst, (c if dst is b else b)
+        torch.cuda.synchronize()
+        assert torch.equal(a, src), f"one call of 12 != 12 single peels ({border})"
+        em.peel(inp, b, H, W, 5, border=border)
+        em.peel(b, c, H, W, 7, border=border)
+        torch.cuda.synchronize()
+        assert torch.equal(a, c), f"5 then 7 != 12 ({border})"
