@@ -47,7 +47,8 @@
  *     null stream) and returns once the work is enqueued. Inputs must stay
  *     valid and unmodified until the stream reaches the work.
  *   - Argument errors are returned before any HIP call is made.
- *   - height == 0 or width == 0 is a no-op returning EDGE_OK.
+ *   - height == 0 or width == 0 is a no-op returning EDGE_OK. Heights above
+ *     EDGE_MAX_HEIGHT and widths above 2^31 - 1 pixels are rejected.
  *   - In-place operation is not supported: overlapping input and output
  *     byte ranges return EDGE_ERR_ALIAS.
  *   - Pointers must be aligned to B/8 bytes (EDGE_ERR_ALIGN otherwise).
@@ -66,6 +67,9 @@ extern "C" {
 #endif
 
 #define EDGE_MASKS_ABI_VERSION 1
+
+/* Largest image height (rows) any entry point accepts. */
+#define EDGE_MAX_HEIGHT (1 << 30)
 
 /* Status codes returned by every int-returning entry point. */
 enum {
@@ -216,8 +220,8 @@ int edge_default_cfg(int64_t height, int64_t width, int word_bits, int mode,
 int64_t edge_batch_workspace_bytes(int32_t n_images);
 
 /* Host-side check of a descriptor table (host memory) against arenas of
- * arena_words words: sizes >= 0, stride >= Wd, every image inside the
- * arena. Returns EDGE_OK or EDGE_ERR_INVALID. */
+ * arena_words words: sizes >= 0, height <= EDGE_MAX_HEIGHT, stride >= Wd,
+ * every image inside the arena. Returns EDGE_OK or EDGE_ERR_INVALID. */
 int edge_batch_check(const edge_image_desc* table_host, int32_t n_images,
                      int64_t arena_words, int word_bits);
 

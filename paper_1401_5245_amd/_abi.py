@@ -28,6 +28,7 @@ EDGE_FLAG_INVERT_OUT = 1 << 1
 EDGE_FLAG_PLANNED = 1 << 2
 EDGE_FLAG_PEEL_EDGE = 1 << 3
 EDGE_PEEL_MAX_ITERATIONS = 30
+EDGE_MAX_HEIGHT = 1 << 30
 
 c_i32, c_i64, c_u32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p
 

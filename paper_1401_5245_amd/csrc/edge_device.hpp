@@ -34,6 +34,9 @@
 namespace edgek {
 
 constexpr int kWave = 64;
+// Row indices are 32-bit in the kernels, and the row loops look a few
+// hundred rows ahead of the last row; images are limited to 2^30 rows.
+constexpr int32_t kMaxHeight = 1 << 30;
 constexpr int kNarrowSteps = 4; // narrow-unit steps loaded ahead of use
 constexpr int kNarrowMaxWords = 32;
 
@@ -92,7 +95,7 @@ __device__ __forceinline__ uint32_t threshold_word(const u32x4& a, const u32x4& 
 
 // Bits of word j that hold pixels x < width.
 __device__ __forceinline__ uint32_t valid_bits(int j, int32_t width) {
-    const int v = width - 32 * j;
+    const int64_t v = (int64_t)width - 32ll * j;
     if (v >= 32) return 0xffffffffu;
     if (v <= 0) return 0u;
     return (1u << (uint32_t)v) - 1u;

@@ -17,6 +17,8 @@
 
 using namespace edgek;
 
+static_assert(kMaxHeight == EDGE_MAX_HEIGHT, "one height limit for the header and the kernels");
+
 // ================================================================ kernels ===
 
 // One image, strips of `rows` rows x 64*VW words, one wavefront per strip.
@@ -87,6 +89,7 @@ __global__ void __launch_bounds__(512) k_narrow(Geom g, int64_t band, int64_t nu
 __host__ __device__ static inline bool desc_ok(const edge_image_desc& d, int64_t arena_words,
                                                int word_bits) {
     if (d.height < 0 || d.width < 0 || d.offset_words < 0 || d.stride_words < 0) return false;
+    if (d.height > kMaxHeight) return false;
     if (d.height == 0 || d.width == 0) return true;
     const int shift = word_bits == 64 ? 6 : 5;
     const int64_t wd = ((int64_t)d.width + word_bits - 1) >> shift;
@@ -325,7 +328,7 @@ __global__ void __launch_bounds__(256) k_pack(const uint8_t* grey, int64_t gstri
     const int64_t y = t / wd;
     const int j = (int)(t - y * wd);
     const uint8_t* rp = grey + y * gstride;
-    const int x0 = 32 * j;
+    const int64_t x0 = 32ll * j;
     uint32_t word = 0;
     if (VEC && x0 + 32 <= width) {
         const u32x4 a = *reinterpret_cast<const u32x4*>(rp + x0);
@@ -448,6 +451,11 @@ bool cfg_ok(const edge_launch_cfg& c) {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// A dispatch carries its grid size in work-items as a 32-bit number.
+bool grid_fits(int64_t blocks, int64_t threads_per_block) {
+    return blocks >= 0 && blocks * threads_per_block <= (int64_t)UINT32_MAX;
+}
+
 int64_t pow2_floor(int64_t v) {
     int64_t p = 1;
     while (p * 2 <= v) p *= 2;
@@ -548,7 +556,7 @@ int launch_single(const Geom& g, int vw, const edge_launch_cfg& c, uint32_t bw, 
         const int64_t band = (int64_t)(kWave / g.wd) * c.rows_per_tile;
         const int64_t nunits = ceil_div(g.height, band);
         const int64_t blocks = ceil_div(nunits, c.waves_per_block);
-        if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+        if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
         hipLaunchKernelGGL(k_narrow<MODE>, dim3((uint32_t)blocks), dim3(threads), 0, stream, g,
                            band, nunits, bw, invert);
         return launch_status();
@@ -556,7 +564,7 @@ int launch_single(const Geom& g, int vw, const edge_launch_cfg& c, uint32_t bw, 
     const int64_t chunks = ceil_div(g.wd, (int64_t)kWave * vw);
     const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
     const int64_t blocks = ceil_div(nunits, c.waves_per_block);
-    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+    if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
     bool stream_mode = c.cache_policy == EDGE_CACHE_STREAM;
     if (c.cache_policy == EDGE_CACHE_AUTO)
         stream_mode = 2 * (int64_t)g.height * g.wd * 4 >= kStreamBytes;
@@ -574,7 +582,7 @@ int image_launch(const void* in, void* out, int64_t height, int64_t width, int64
     int rc = common_checks(word_bits, border, mode, flags);
     if (rc) return rc;
     if (height < 0 || width < 0 || stride_words < 0 || plane_words < 0) return EDGE_ERR_INVALID;
-    if (height > 0x7fffffff || width > 0x7fffffff) return EDGE_ERR_INVALID;
+    if (height > kMaxHeight || width > 0x7fffffff) return EDGE_ERR_INVALID;
     if (cfg && !cfg_ok(*cfg)) return EDGE_ERR_INVALID;
     if (height == 0 || width == 0) return EDGE_OK;
     if (!in || !out) return EDGE_ERR_INVALID;
@@ -723,7 +731,7 @@ int launch_grey_part(const Geom& g, const edge_launch_cfg& c, int64_t chunk0, in
     if (chunks <= 0) return EDGE_OK;
     const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
     const int64_t blocks = ceil_div(nunits, c.waves_per_block);
-    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+    if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
     hipLaunchKernelGGL((k_strip_grey<MODE, Pol, TAIL>), dim3((uint32_t)blocks),
                        dim3(c.waves_per_block * kWave), 0, stream, g, chunk0, chunks,
                        c.rows_per_tile, nunits, bw, invert);
@@ -761,7 +769,7 @@ int launch_peel_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, hip
     const int64_t chunks = ceil_div(g.wd, (int64_t)kPeelSpan);
     const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
     const int64_t blocks = ceil_div(nunits, c.waves_per_block);
-    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+    if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
     hipLaunchKernelGGL((k_peel<L, EDGEOUT, COPY, CachedStrip>), dim3((uint32_t)blocks),
                        dim3(c.waves_per_block * kWave), 0, s, g, chunks, c.rows_per_tile, nunits,
                        bw);
@@ -796,6 +804,8 @@ edge_launch_cfg default_peel(int64_t height, int64_t wd32, int iterations) {
     int64_t rows = 8;
     while (rows < 2 * iterations && rows < 64) rows *= 2;
     if (rows < 64 && chunks * ceil_div(height, rows) > 8192) rows *= 2;
+    // keep the grid (one wavefront per strip) within 2^32 work-items
+    while (chunks * ceil_div(height, rows) >= (1ll << 26) && rows < 1024) rows *= 2;
     c.rows_per_tile = (int32_t)rows;
     return c;
 }
@@ -804,7 +814,7 @@ template <int STAGE>
 int launch_stage(const uint32_t* img, const uint32_t* src, uint32_t* dst, int64_t stride,
                  int32_t height, int32_t width, int32_t wd, uint32_t bw, hipStream_t s) {
     const int64_t blocks = ceil_div((int64_t)height * wd, 256);
-    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+    if (!grid_fits(blocks, 256)) return EDGE_ERR_UNSUPPORTED;
     hipLaunchKernelGGL(k_stage<STAGE>, dim3((uint32_t)blocks), dim3(256), 0, s, img, src, dst,
                        stride, height, width, wd, bw);
     return launch_status();
@@ -866,7 +876,7 @@ int edge_threshold_pack(const void* grey, int64_t grey_stride_bytes, int thresho
     if (threshold < 0 || threshold > 256) return EDGE_ERR_INVALID;
     if (height < 0 || width < 0 || stride_words < 0 || grey_stride_bytes < 0)
         return EDGE_ERR_INVALID;
-    if (height > 0x7fffffff || width > 0x7fffffff) return EDGE_ERR_INVALID;
+    if (height > kMaxHeight || width > 0x7fffffff) return EDGE_ERR_INVALID;
     if (height == 0 || width == 0) return EDGE_OK;
     if (!grey || !out) return EDGE_ERR_INVALID;
     const int64_t wd = ceil_div(width, word_bits);
@@ -883,7 +893,7 @@ int edge_threshold_pack(const void* grey, int64_t grey_stride_bytes, int thresho
     const int32_t wd32 = (int32_t)(wd * per);
     const int64_t threads = height * (int64_t)wd32;
     const int64_t blocks = ceil_div(threads, 256);
-    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+    if (!grid_fits(blocks, 256)) return EDGE_ERR_UNSUPPORTED;
     const bool vec = (uintptr_t)grey % 16 == 0 && grey_stride_bytes % 16 == 0;
     hipStream_t s = (hipStream_t)hip_stream;
     if (vec)
@@ -908,7 +918,7 @@ int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int thresh
     if (threshold < 0 || threshold > 256) return EDGE_ERR_INVALID;
     if (height < 0 || width < 0 || stride_words < 0 || grey_stride_bytes < 0)
         return EDGE_ERR_INVALID;
-    if (height > 0x7fffffff || width > 0x7fffffff) return EDGE_ERR_INVALID;
+    if (height > kMaxHeight || width > 0x7fffffff) return EDGE_ERR_INVALID;
     if (cfg && !cfg_ok(*cfg)) return EDGE_ERR_INVALID;
     if (height == 0 || width == 0) return EDGE_OK;
     if (!grey || !out) return EDGE_ERR_INVALID;
@@ -965,7 +975,7 @@ int edge_peel(const void* in, void* out, int64_t height, int64_t width, int64_t 
     if (flags & ~(uint32_t)EDGE_FLAG_PEEL_EDGE) return EDGE_ERR_INVALID;
     if (iterations < 0 || iterations > EDGE_PEEL_MAX_ITERATIONS) return EDGE_ERR_INVALID;
     if (height < 0 || width < 0 || stride_words < 0) return EDGE_ERR_INVALID;
-    if (height > 0x7fffffff || width > 0x7fffffff) return EDGE_ERR_INVALID;
+    if (height > kMaxHeight || width > 0x7fffffff) return EDGE_ERR_INVALID;
     if (cfg && !cfg_ok(*cfg)) return EDGE_ERR_INVALID;
     if (height == 0 || width == 0) return EDGE_OK;
     if (!in || !out) return EDGE_ERR_INVALID;
@@ -1003,7 +1013,7 @@ int edge_masks_staged(const void* in, void* out, void* scratch, int64_t scratch_
     if (word_bits != 32 && word_bits != 64) return EDGE_ERR_INVALID;
     if (border != EDGE_BORDER_WHITE && border != EDGE_BORDER_BLACK) return EDGE_ERR_INVALID;
     if (height < 0 || width < 0 || stride_words < 0 || scratch_bytes < 0) return EDGE_ERR_INVALID;
-    if (height > 0x7fffffff || width > 0x7fffffff) return EDGE_ERR_INVALID;
+    if (height > kMaxHeight || width > 0x7fffffff) return EDGE_ERR_INVALID;
     if (height == 0 || width == 0) return EDGE_OK;
     if (!in || !out) return EDGE_ERR_INVALID;
     const int64_t wd = ceil_div(width, word_bits);
@@ -1194,7 +1204,7 @@ int edge_copy_bytes(const void* in, void* out, int64_t n_bytes, void* hip_stream
         return EDGE_ERR_ALIAS;
     const int64_t n16 = n_bytes / 16;
     const int64_t blocks = ceil_div(n16, 256 * 4);
-    if (blocks > 0x7fffffff) return EDGE_ERR_UNSUPPORTED;
+    if (!grid_fits(blocks, 256)) return EDGE_ERR_UNSUPPORTED;
     hipLaunchKernelGGL(k_copy, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)hip_stream,
                        (const u32x4*)in, (u32x4*)out, n16);
     return launch_status();

@@ -57,7 +57,8 @@ def launch(inp=A, out=B, H=4, W=100, S=4, wb=32, border=0, mode=0, flags=0, cfg=
     (dict(inp=None), INVALID), (dict(out=None), INVALID),
     (dict(inp=A + 2), ALIGN), (dict(out=B + 4, wb=64, S=2), ALIGN),
     (dict(out=A + 16), ALIAS), (dict(out=A - 4 * 15), ALIAS),
-    (dict(H=1 << 31), INVALID),
+    (dict(H=1 << 31), INVALID), (dict(H=_abi.EDGE_MAX_HEIGHT + 1), INVALID),
+    (dict(W=1 << 31, S=1 << 26), INVALID),
 ])
 def test_image_validation(kw, want):
     assert masks(**kw) == want
@@ -95,6 +96,7 @@ def peel(inp=A, out=B, H=4, W=100, S=4, wb=32, border=0, k=3, flags=0, cfg=None)
     (dict(flags=_abi.EDGE_FLAG_PEEL_EDGE | _abi.EDGE_FLAG_INVERT_OUT), INVALID),
     (dict(cfg=ctypes.byref(_abi.EdgeLaunchCfg(4, 0, 4, 1, 0))), INVALID),
     (dict(H=0), OK), (dict(W=0, inp=None, out=None), OK),
+    (dict(H=_abi.EDGE_MAX_HEIGHT + 1), INVALID),
 ])
 def test_peel_validation(kw, want):
     assert peel(**kw) == want
@@ -121,6 +123,10 @@ def test_batch_check():
     ok = table([(0, 10, 40, 2), (20, 5, 64, 2), (30, 0, 0, 0), (31, 3, 1, 1)])
     assert lib.edge_batch_check(ok.ctypes.data, len(ok), 34, 32) == OK
     assert lib.edge_batch_check(ok.ctypes.data, len(ok), 33, 32) == INVALID  # last image overruns
+    tall = (0, _abi.EDGE_MAX_HEIGHT + 1, 1, 1)             # inside an arena of 2^30 + 1 words
+    assert lib.edge_batch_check(table([tall]).ctypes.data, 1, (1 << 30) + 1, 32) == INVALID
+    assert lib.edge_batch_check(table([(0, 1 << 30, 1, 1)]).ctypes.data, 1, (1 << 30) + 1,
+                                32) == OK
     for bad in [(0, -1, 4, 1), (0, 1, -4, 1), (-1, 1, 4, 1), (0, 2, 40, 1), (0, 2, 32, 1 << 40)]:
         t = table([bad])
         assert lib.edge_batch_check(t.ctypes.data, 1, 1000, 32) == INVALID, bad
