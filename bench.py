@@ -254,6 +254,19 @@ def copy_ceiling(torch, em, tm, nbytes, nb, steps):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def launch_floor_ms(torch, em, tm, nl=40, reps=5):
+    """Per-launch time of a near-empty kernel (the library's copy of 16
+    bytes: one workgroup) replayed from a one-stream graph, as the headline
+    launches are: the fixed cost any launch pays."""
+    a = torch.zeros(2, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    g = graph_of(torch, lambda: [em.copy_bytes(a, b, 16) for _ in range(nl)])
+    g.replay()
+    ms = tm.per_call_ms(lambda i: g.replay(), reps) / nl
+    del g
+    return ms
+
+
 def plain_512(torch, em, tm, steps):
     from synth import images, pack_rows, unpack_rows
     import oracle
@@ -428,8 +441,12 @@ def serving(torch, em, p99_bound_ms=20.0, budget=4 << 30):
             st["offered_rps"] = rate
             st["trials_p99_ms"] = [t["p99_ms"] for t in trials]
             runs.append(st)
+            st["trials_host_stall_ms"] = [max(t["max_loop_pass_ms"], t["max_oversleep_ms"])
+                                          for t in trials]
             log(f"serve {name} rate={rate:.0f}/s p50={st['p50_ms']} p99={st['trials_p99_ms']} "
-                f"gpx_s={st['gpx_s']} batches={st['batches']}")
+                f"gpx_s={st['gpx_s']} batches={st['batches']} "
+                f"host stall ms={st['trials_host_stall_ms']} "
+                f"sections={[t['max_section_ms'] for t in trials]}")
             if st["p99_ms"] <= p99_bound_ms:
                 best = st
         out[name] = {"runs": runs,
@@ -887,6 +904,10 @@ def main():
     copy16 = copy_ceiling(torch, em, tm, 8 << 20, 40, args.steps)
     res["roofline"]["copy_gbs_same_bytes"] = round(copy16, 1)
     res["roofline"]["frac_of_copy"] = round(res["roofline"]["achieved"] / copy16, 3)
+    floor = launch_floor_ms(torch, em, tm)
+    res["roofline"]["launch_floor_us"] = round(floor * 1e3, 2)
+    if kernel_ms > floor:     # bandwidth of the part of a launch above the fixed cost
+        res["roofline"]["gbs_above_launch_floor"] = round(nbytes / ((kernel_ms - floor) * 1e-3) / 1e9, 1)
     if not args.headline_only:
         extra = {}
         extra["copy_ceiling_gbs_1GiB"] = round(copy_ceiling(torch, em, tm, 512 << 20, 2, 20), 1)

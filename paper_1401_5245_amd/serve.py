@@ -27,6 +27,39 @@ import torch
 from . import batch as _batch
 from ._abi import EdgeError, EDGE_ERR_INVALID
 
+_HIP = None
+
+
+def _hip():
+    """The HIP runtime already loaded by torch (copies are issued with
+    hipMemcpyAsync directly: torch's non-blocking copies into pinned memory
+    also record a tracking event per copy, which can stall the host)."""
+    global _HIP
+    if _HIP is None:
+        import ctypes
+        lib = ctypes.CDLL("libamdhip64.so")
+        lib.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_int, ctypes.c_void_p]
+        lib.hipMemcpyAsync.restype = ctypes.c_int
+        _HIP = lib
+    return _HIP
+
+
+_HIP_MEMCPY_DEFAULT = 4     # direction inferred from the pointers (unified addressing)
+
+
+def _copy_async(dst: torch.Tensor, dst_off: int, src: torch.Tensor, src_off: int, n: int,
+                stream: torch.cuda.Stream) -> None:
+    """Copy n elements src[src_off:] -> dst[dst_off:] on `stream`."""
+    if not (0 <= src_off and src_off + n <= src.numel() and 0 <= dst_off
+            and dst_off + n <= dst.numel()):
+        raise ValueError("copy outside its tensors")
+    es = src.element_size()
+    rc = _hip().hipMemcpyAsync(dst.data_ptr() + dst_off * es, src.data_ptr() + src_off * es,
+                               n * es, _HIP_MEMCPY_DEFAULT, stream.cuda_stream)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+
 
 class RingArena:
     """FIFO ring allocator over [0, capacity) words.
@@ -91,7 +124,6 @@ class Request:
     done: float = -1.0
     offset: int = -1                 # device arena offset (words)
     rejected: bool = False
-    ev_in: object = None             # event after the copy that brought it in
 
 
 @dataclass
@@ -168,7 +200,8 @@ class Server:
     """One-GPU continuous-batching server over a pinned request pool."""
 
     def __init__(self, pool: Pool, budget_bytes: int, *, max_inflight: int = 3,
-                 max_batch: int = 4096, border: str = "white", mode: str = "masks",
+                 max_batch: int = 4096, max_batch_bytes: int = 64 << 20,
+                 border: str = "white", mode: str = "masks",
                  cfg=None, device="cuda"):
         self.pool = pool
         wb = pool.word_bits
@@ -182,6 +215,9 @@ class Server:
         self.dev_out = torch.zeros(cap, dtype=dt, device=device)
         self.max_inflight = max_inflight
         self.max_batch = max_batch
+        # bytes of input per batch: a burst of arrivals then becomes several
+        # pipelined batches instead of one whose copies hold up the rest
+        self.max_batch_words = max(1, int(max_batch_bytes) // self.word_bytes)
         self.kw = dict(border=border, mode=mode, cfg=cfg)
         self.s_in = torch.cuda.Stream(device)
         self.s_k = torch.cuda.Stream(device)
@@ -194,8 +230,26 @@ class Server:
                 "table_dev": torch.zeros(max_batch * 3, dtype=torch.int64, device=device),
                 "plan_host": torch.zeros(-(-nb // 8), dtype=torch.int64).pin_memory(),
                 "ws": torch.zeros(-(-nb // 8), dtype=torch.int64, device=device),
+                # created once and re-recorded each time the slot is used: the
+                # slot is reused only after its last batch is back on the host
+                "ev_in": torch.cuda.Event(), "ev_k": torch.cuda.Event(),
+                "ev_d": torch.cuda.Event(),
                 "busy": False})
         self._tab = np.zeros(max_batch, dtype=_batch.DESC_DTYPE)
+        self.warmup()
+
+    def warmup(self):
+        """Run the copy paths once at full size (pool to arena and back, on
+        the serving streams) so that first-use set-up in the runtime is not
+        paid by a request."""
+        n = min(self.pool.host_in.numel(), self.dev_in.numel())
+        _copy_async(self.dev_in, 0, self.pool.host_in, 0, n, self.s_in)
+        self.s_out.wait_stream(self.s_in)
+        _copy_async(self.pool.host_out, 0, self.dev_in, 0, n, self.s_out)
+        for S in self.slots:
+            for k in ("ev_in", "ev_k", "ev_d"):
+                S[k].record(self.s_out)
+        torch.cuda.synchronize()
 
     # ---------------------------------------------------------------- loop --
 
@@ -228,9 +282,20 @@ class Server:
         dev_in, dev_out, host_in, host_out = self.dev_in, self.dev_out, pool.host_in, pool.host_out
         table = pool.table
         rejected = 0
+        # host-side stalls: the longest pass through the loop, and the most a
+        # sleep overran what it asked for
+        max_pass, max_oversleep, stalls_over_1ms = 0.0, 0.0, 0
+        sect = collections.defaultdict(float)       # longest time in each part of a pass
+
+        def mark(name, t_from):
+            t_to = now()
+            if t_to - t_from > sect[name]:
+                sect[name] = t_to - t_from
+            return t_to
 
         while waiting or admitted or inflight:
             progressed = False
+            it = now()
             # 1. completions, oldest first (the ring frees in order)
             while inflight and inflight[0].ev_done.query():
                 b = inflight.popleft()
@@ -249,7 +314,7 @@ class Server:
                     for r in b.reqs:
                         r.kernel_done = t
             # 2. admission in arrival order while the ring has room
-            t = now()
+            t = mark("completions", it)
             newly = []
             while waiting and reqs[waiting[0]].arrival <= t:
                 r = reqs[waiting[0]]
@@ -272,28 +337,31 @@ class Server:
             if newly:
                 runs = _runs([int(table[r.pool_index]["offset_words"]) for r in newly],
                              [r.offset for r in newly], [int(words[r.rid]) for r in newly])
-                with torch.cuda.stream(self.s_in):
-                    for s, d, m in runs:
-                        dev_in[d:d + m].copy_(host_in[s:s + m], non_blocking=True)
-                    ev = torch.cuda.Event()
-                    ev.record(self.s_in)
-                for r in newly:
-                    r.ev_in = ev
+                for s, d, m in runs:
+                    _copy_async(dev_in, d, host_in, s, m, self.s_in)
                 admitted.extend(newly)
                 progressed = True
             # 3. launch: every admitted request not yet launched (continuous batching)
+            t_s = mark("admission", t)
             if admitted:
                 slot = next((i for i, s in enumerate(self.slots) if not s["busy"]), None)
                 if slot is not None:
-                    take = 1 if per_request else min(len(admitted), self.max_batch)
-                    group = [admitted.popleft() for _ in range(take)]
-                    seen = set()
-                    for r in group:                 # the copies that brought the group in
-                        if id(r.ev_in) not in seen:
-                            seen.add(id(r.ev_in))
-                            self.s_k.wait_event(r.ev_in)
+                    if per_request:
+                        group = [admitted.popleft()]
+                    else:
+                        group, gw = [], 0
+                        while admitted and len(group) < self.max_batch and (
+                                not group or gw + words[admitted[0].rid] <= self.max_batch_words):
+                            r = admitted.popleft()
+                            gw += words[r.rid]
+                            group.append(r)
                     S = self.slots[slot]
+                    # the copy-in stream is in order: one event recorded now
+                    # covers the copies of every request admitted so far
+                    S["ev_in"].record(self.s_in)
+                    self.s_k.wait_event(S["ev_in"])
                     t = now()
+                    t_s = mark("launch_wait", t_s)
                     with torch.cuda.stream(self.s_k):
                         if per_request:
                             r = group[0]
@@ -320,34 +388,45 @@ class Server:
                                                         mode=self.kw["mode"],
                                                         cfg=self.kw["cfg"], out=ph.numpy())
                             nw = -(-used // 8)
-                            S["table_dev"][:k * 3].copy_(th[:k * 3], non_blocking=True)
-                            S["ws"][:nw].copy_(ph[:nw], non_blocking=True)
+                            t_s = mark("plan", t_s)
+                            _copy_async(S["table_dev"], 0, th, 0, k * 3, self.s_k)
+                            _copy_async(S["ws"], 0, ph, 0, nw, self.s_k)
+                            t_s = mark("plan_copy", t_s)
                             _batch.edge_batch(dev_in, dev_out, S["table_dev"], k, S["ws"],
                                               planned=True, stream=self.s_k, **self.kw)
-                        ev_k = torch.cuda.Event()
+                            t_s = mark("batch_launch", t_s)
+                        ev_k = S["ev_k"]
                         ev_k.record(self.s_k)
                     self.s_out.wait_event(ev_k)
                     runs = _runs([r.offset for r in group],
                                  [int(table[r.pool_index]["offset_words"]) for r in group],
                                  [int(words[r.rid]) for r in group])
-                    with torch.cuda.stream(self.s_out):
-                        for s, d, m in runs:
-                            host_out[d:d + m].copy_(dev_out[s:s + m], non_blocking=True)
-                        ev_d = torch.cuda.Event()
-                        ev_d.record(self.s_out)
+                    for s, d, m in runs:
+                        _copy_async(host_out, d, dev_out, s, m, self.s_out)
+                    ev_d = S["ev_d"]
+                    ev_d.record(self.s_out)
+                    mark("copy_out", t_s)
                     for r in group:
                         r.launched = t
                     S["busy"] = True
                     inflight.append(_Batch(group, slot, ev_k, ev_d))
                     nbatches += 1
                     progressed = True
+            t_end = now()
+            if t_end - it > max_pass:
+                max_pass = t_end - it
+            stalls_over_1ms += t_end - it > 1e-3
             if not progressed:
+                want = 0.0
                 if not admitted and not inflight and waiting:
-                    gap = reqs[waiting[0]].arrival - now()
+                    gap = reqs[waiting[0]].arrival - t_end
                     if gap > 2e-4:
-                        time.sleep(gap - 1e-4)
-                else:
-                    time.sleep(0)
+                        want = gap - 1e-4
+                time.sleep(want)
+                over = now() - t_end - want
+                if over > max_oversleep:
+                    max_oversleep = over
+                stalls_over_1ms += over > 1e-3
         served = [r for r in reqs if not r.rejected and words[r.rid] > 0]
         lat = np.array([(r.done - r.arrival) * 1e3 for r in served])
         lat_k = np.array([((r.kernel_done if r.kernel_done >= 0 else r.done) - r.arrival) * 1e3
@@ -356,7 +435,11 @@ class Server:
         pixels = int(sum(int(pool.pixels[r.pool_index]) for r in served))
         t_first = min((r.arrival for r in served), default=0.0)
         t_last = max((r.done for r in served), default=0.0)
-        st = Stats(lat, lat_k, queue, pixels, t_last - t_first, nbatches, rejected)
+        st = Stats(lat, lat_k, queue, pixels, t_last - t_first, nbatches, rejected,
+                   {"max_loop_pass_ms": round(max_pass * 1e3, 3),
+                    "max_oversleep_ms": round(max_oversleep * 1e3, 3),
+                    "host_stalls_over_1ms": int(stalls_over_1ms),
+                    "max_section_ms": {k: round(v * 1e3, 3) for k, v in sect.items()}})
         if record_outputs:
             st.extra["outputs"] = out_of
         return st
