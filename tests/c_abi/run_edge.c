@@ -1,0 +1,121 @@
+/* The library driven from plain C: device memory from the HIP runtime's C
+ * API, no Python and no PyTorch. Each case runs an entry point on a seeded
+ * random image and compares every pixel with the oracle's C functions (this
+ * program is test infrastructure, so it may call both). Prints one line per
+ * case; exits 0 when every case matches. */
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "edge_masks.h"
+
+/* oracle/edge_oracle.c */
+int oracle_edge_image(const uint8_t* img, uint8_t* out, int64_t H, int64_t W, int border_pixel,
+                      int clauses, int invert);
+int oracle_peel(const uint8_t* img, uint8_t* out, int64_t H, int64_t W, int border_pixel,
+                int iterations, int edge_out);
+
+static uint64_t rng_state;
+
+static uint64_t next_u64(void) { /* splitmix64 */
+    uint64_t z = (rng_state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+#define HIP_OK(x)                                                             \
+    do {                                                                      \
+        hipError_t e_ = (x);                                                  \
+        if (e_ != hipSuccess) {                                               \
+            printf("HIP error %d at line %d\n", (int)e_, __LINE__);          \
+            return 0;                                                         \
+        }                                                                     \
+    } while (0)
+
+enum { KIND_MASKS, KIND_FULL, KIND_PEEL };
+
+/* One case: returns 1 when the device output equals the oracle's. */
+static int run_case(int64_t H, int64_t W, int border, int kind, uint64_t seed) {
+    const int64_t wd = (W + 63) / 64, S = wd + 1, n = H * S;
+    const uint64_t sentinel = 0xA5A5A5A5A5A5A5A5ull;
+    uint64_t* words = malloc((size_t)n * 8);
+    uint64_t* back = malloc((size_t)n * 8);
+    uint8_t* img = malloc((size_t)(H * W));
+    uint8_t* want = malloc((size_t)(H * W));
+    void *din = NULL, *dout = NULL;
+    int ok = 1, rc = EDGE_OK;
+    int64_t y, x;
+    rng_state = seed;
+    for (int64_t i = 0; i < n; ++i) words[i] = next_u64() & next_u64(); /* ~25% white */
+    for (y = 0; y < H; ++y)
+        for (x = 0; x < W; ++x) img[y * W + x] = (uint8_t)((words[y * S + x / 64] >> (x % 64)) & 1);
+    HIP_OK(hipMalloc(&din, (size_t)n * 8));
+    HIP_OK(hipMalloc(&dout, (size_t)n * 8));
+    HIP_OK(hipMemcpy(din, words, (size_t)n * 8, hipMemcpyHostToDevice));
+    HIP_OK(hipMemset(dout, 0xA5, (size_t)n * 8));
+    if (kind == KIND_MASKS) {
+        rc = edge_masks(din, dout, H, W, S, 64, border, NULL);
+        oracle_edge_image(img, want, H, W, border == EDGE_BORDER_WHITE, 1, 0);
+    } else if (kind == KIND_FULL) {
+        rc = edge_full(din, dout, H, W, S, 64, border, 0u, NULL);
+        oracle_edge_image(img, want, H, W, border == EDGE_BORDER_WHITE, 3, 0);
+    } else {
+        rc = edge_peel(din, dout, H, W, S, 64, border, 3, 0u, NULL, NULL);
+        oracle_peel(img, want, H, W, border == EDGE_BORDER_WHITE, 3, 0);
+    }
+    if (rc != EDGE_OK) {
+        printf("entry point returned %d (%s)\n", rc, edge_status_string(rc));
+        ok = 0;
+    }
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipMemcpy(back, dout, (size_t)n * 8, hipMemcpyDeviceToHost));
+    for (y = 0; y < H && ok; ++y) {
+        for (x = 0; x < W; ++x)
+            if ((uint8_t)((back[y * S + x / 64] >> (x % 64)) & 1) != want[y * W + x]) {
+                printf("pixel (%lld, %lld) differs\n", (long long)y, (long long)x);
+                ok = 0;
+                break;
+            }
+        if (ok && W % 64 && (back[y * S + wd - 1] >> (W % 64)) != 0) {
+            printf("row %lld: pad bits not zero\n", (long long)y);
+            ok = 0;
+        }
+        if (ok && back[y * S + wd] != sentinel) {
+            printf("row %lld: stride word written\n", (long long)y);
+            ok = 0;
+        }
+    }
+    /* in place is refused before any HIP call */
+    if (ok && edge_masks(din, din, H, W, S, 64, border, NULL) != EDGE_ERR_ALIAS) ok = 0;
+    HIP_OK(hipFree(din));
+    HIP_OK(hipFree(dout));
+    free(words);
+    free(back);
+    free(img);
+    free(want);
+    printf("%s %lld x %lld border %d kind %d\n", ok ? "match" : "MISMATCH", (long long)H,
+           (long long)W, border, kind);
+    return ok;
+}
+
+int main(void) {
+    static const int64_t shapes[][2] = {{1, 1}, {3, 33}, {5, 64}, {70, 1000}, {257, 2049},
+                                        {33, 8193}};
+    int all = 1, cases = 0;
+    if (edge_abi_version() != EDGE_MASKS_ABI_VERSION) {
+        printf("ABI version mismatch\n");
+        return 1;
+    }
+    for (size_t s = 0; s < sizeof(shapes) / sizeof(shapes[0]); ++s)
+        for (int border = 0; border < 2; ++border)
+            for (int kind = 0; kind < 3; ++kind) {
+                all &= run_case(shapes[s][0], shapes[s][1], border, kind,
+                                1000u * (uint64_t)s + 10u * (uint64_t)border + (uint64_t)kind);
+                ++cases;
+            }
+    printf("%s: %d cases\n", all ? "all match" : "FAILED", cases);
+    return all ? 0 : 1;
+}
