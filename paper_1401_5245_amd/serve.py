@@ -432,11 +432,22 @@ class Server:
         lat_k = np.array([((r.kernel_done if r.kernel_done >= 0 else r.done) - r.arrival) * 1e3
                           for r in served])
         queue = np.array([(r.launched - r.arrival) * 1e3 for r in served])
+        # stages: waiting for a launch slot (and its copy-in), copy-in + kernel
+        # as seen by the host, copy-out
+        k_seen = np.array([((r.kernel_done if r.kernel_done >= 0 else r.done) - r.launched) * 1e3
+                           for r in served])
+        d2h = np.array([(r.done - (r.kernel_done if r.kernel_done >= 0 else r.done)) * 1e3
+                        for r in served])
         pixels = int(sum(int(pool.pixels[r.pool_index]) for r in served))
         t_first = min((r.arrival for r in served), default=0.0)
         t_last = max((r.done for r in served), default=0.0)
+        pct = (lambda a, p: round(float(np.percentile(a, p)), 3) if a.size else None)
+        stages = {"launch_to_kernel_done_ms": [pct(k_seen, 50), pct(k_seen, 99)],
+                  "copy_out_ms": [pct(d2h, 50), pct(d2h, 99)],
+                  "queue_ms": [pct(queue, 50), pct(queue, 99)]}
         st = Stats(lat, lat_k, queue, pixels, t_last - t_first, nbatches, rejected,
-                   {"max_loop_pass_ms": round(max_pass * 1e3, 3),
+                   {"stages_p50_p99": stages,
+                    "max_loop_pass_ms": round(max_pass * 1e3, 3),
                     "max_oversleep_ms": round(max_oversleep * 1e3, 3),
                     "host_stalls_over_1ms": int(stalls_over_1ms),
                     "max_section_ms": {k: round(v * 1e3, 3) for k, v in sect.items()}})
