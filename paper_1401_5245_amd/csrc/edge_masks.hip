@@ -490,10 +490,15 @@ int alignment_words(uintptr_t p) {
     return 1;
 }
 
-// Built-in single-image shape. Rows of <= 32 words: narrow units of up to
-// 16 steps. Wider rows: about 2048 strips (8 wavefronts per compute unit,
-// one workgroup of 8 each when there are enough rows), each at least 2 and
-// at most 256 rows tall.
+// Built-in single-image shape, from the tuned shapes of square images of
+// 2048^2 .. 65536^2 on gfx950. Rows of <= 32 words: narrow units of up to 16
+// steps. Wider rows: four words per lane when the row fills at least 75% of
+// its 256-word spans, else two (a half-used 4-word span loses to twice the
+// wavefronts: 3.1 against 4.4 us at 4096^2, 5.2 against 7.1 us at 6000^2).
+// Images of up to 16 MiB of traffic are bound by launch latency and take
+// 2-row strips (the most wavefronts); larger ones take about 1024 strips
+// (at most 256 rows each), so that every wavefront walks far enough to
+// amortise its halo rows.
 edge_launch_cfg default_single(int64_t height, int64_t wd32) {
     edge_launch_cfg c;
     c.blocks_per_cu = 1;
@@ -504,18 +509,21 @@ edge_launch_cfg default_single(int64_t height, int64_t wd32) {
         c.waves_per_block = 4;
         c.rows_per_tile = (int32_t)pow2_floor(std::max<int64_t>(1, std::min<int64_t>(16, height / (grp * 2048))));
     } else {
-        c.vec_words = 4;
-        const int v = pick_vw(wd32, 4, 0, 0);
+        const int64_t span4 = (int64_t)kWave * 4;
+        c.vec_words = 4 * wd32 >= 3 * span4 * ceil_div(wd32, span4) ? 4 : 2;
+        const int v = pick_vw(wd32, c.vec_words, 0, 0);
         const int64_t chunks = ceil_div(wd32, (int64_t)kWave * v);
-        c.rows_per_tile = (int32_t)pow2_floor(std::max<int64_t>(2, std::min<int64_t>(256, chunks * height / 2048)));
-        c.waves_per_block = c.rows_per_tile >= 16 ? 8 : 4;
+        const bool small = 2 * height * wd32 * 4 <= (16ll << 20);
+        c.rows_per_tile = small ? 2 : (int32_t)pow2_floor(std::max<int64_t>(2, std::min<int64_t>(256, chunks * height / 1024)));
+        c.waves_per_block = c.rows_per_tile >= 256 ? 8 : 4;
     }
     return c;
 }
 
 // Streaming (non-temporal) loads and stores pay off from a few MiB of
-// traffic up (measured: 16 MiB and larger); small images stay cached.
-constexpr int64_t kStreamBytes = 8ll << 20;
+// traffic up (measured: 3.12 against 3.30 us at 4096^2, 4 MiB; equal at
+// 3000^2); smaller images stay cached.
+constexpr int64_t kStreamBytes = 4ll << 20;
 
 edge_launch_cfg default_batch() {
     edge_launch_cfg c;

@@ -110,6 +110,15 @@ def test_default_cfg():
     assert lib.edge_default_cfg(-1, 8, 32, 0, 0, ctypes.byref(c)) == INVALID
     assert lib.edge_default_cfg(100, 100, 32, 0, 1, ctypes.byref(c)) == OK
     assert c.blocks_per_cu >= 1
+    # strip heights of the built-in shape: 2 rows up to 16 MiB of traffic,
+    # then about 1024 strips, at most 256 rows
+    for side, rows in ((2048, 2), (8192, 2), (16384, 32), (32768, 128), (65536, 256)):
+        assert lib.edge_default_cfg(side, side, 64, 0, 0, ctypes.byref(c)) == OK
+        assert c.rows_per_tile == rows, (side, c.rows_per_tile)
+    # four words per lane only when the rows fill 75% of their 256-word spans
+    for side, vec in ((4096, 2), (6000, 2), (6200, 4), (8192, 4), (9600, 2), (12800, 4)):
+        assert lib.edge_default_cfg(side, side, 64, 0, 0, ctypes.byref(c)) == OK
+        assert c.vec_words == vec, (side, c.vec_words)
 
 
 def table(rows):
