@@ -36,8 +36,10 @@ def log(*a):
 def parse():
     p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=200)
-    p.add_argument("--warmup", type=int, default=20)
+    # about 22 ms of warm-up and of timed launches at 8192^2: long enough
+    # for the clocks to settle and for one timed region to be stable
+    p.add_argument("--steps", type=int, default=4000)
+    p.add_argument("--warmup", type=int, default=4000)
     p.add_argument("--headline-only", action="store_true",
                    help="time only the headline workload (no other configs, no CPU baseline)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
@@ -389,7 +391,7 @@ def batched_crops(torch, em, tm, steps):
             lib.edge_masks(pi, po, h, w, s, 32, 0, stream)
 
     per_image(0)
-    ms_plain = tm.per_call_ms(per_image, max(3, steps // 50))
+    ms_plain = tm.per_call_ms(per_image, max(3, min(20, steps // 50)))
     return {"workload": "batched, 4096 glyph crops H,W log-uniform [24,256] (seed 3), uint32, "
                         "%.1f Mpx" % (px / 1e6),
             "gpx_s_graph": round(px / (ms_graph * 1e-3) / 1e9, 1),
