@@ -249,7 +249,10 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan(const edge_image_desc* ta
 // (descriptor inside the arena, unit index inside the image), so a plan
 // that does not belong to this table yields wrong output, never an access
 // outside the arenas.
-template <int MODE>
+// VMAX: the widest strip vector width compiled in. VMAX = 1 leaves out the
+// wide strip paths, whose registers would otherwise limit how many
+// wavefronts of small crops a compute unit keeps in flight.
+template <int MODE, int VMAX>
 __global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out,
                                                const edge_image_desc* tab, int n,
                                                int64_t arena_words, int word_bits,
@@ -296,10 +299,12 @@ __global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out
         const int64_t y1 = y0 + s.band < d.height ? y0 + s.band : d.height;
         if (s.narrow) {
             narrow_unit<MODE>(g, (int)y0, (int)y1, bw, invert != 0);
-        } else if (s.vw == 4) {
-            strip_unit<4, MODE>(g, (int)(chunk * kWave * 4), (int)y0, (int)y1, bw, invert != 0);
-        } else if (s.vw == 2) {
-            strip_unit<2, MODE>(g, (int)(chunk * kWave * 2), (int)y0, (int)y1, bw, invert != 0);
+        } else if (VMAX >= 4 && s.vw == 4) {
+            strip_unit<(VMAX >= 4 ? 4 : 1), MODE>(g, (int)(chunk * kWave * 4), (int)y0, (int)y1,
+                                                  bw, invert != 0);
+        } else if (VMAX >= 2 && s.vw == 2) {
+            strip_unit<(VMAX >= 2 ? 2 : 1), MODE>(g, (int)(chunk * kWave * 2), (int)y0, (int)y1,
+                                                  bw, invert != 0);
         } else {
             strip_unit<1, MODE>(g, (int)(chunk * kWave), (int)y0, (int)y1, bw, invert != 0);
         }
@@ -689,9 +694,16 @@ template <int MODE>
 int launch_batch_kernel(const BatchArgs& a, int vmax, int blocks, hipStream_t s) {
     const uint32_t bw = border_word(a.border);
     const int inv = (a.flags & EDGE_FLAG_INVERT_OUT) ? 1 : 0;
-    hipLaunchKernelGGL(k_batch<MODE>, dim3(blocks), dim3(a.cfg.waves_per_block * kWave), 0, s,
-                       (const uint32_t*)a.in, (uint32_t*)a.out, a.table, a.n, a.arena_words,
-                       a.word_bits, (const int64_t*)a.ws, vmax, a.cfg.rows_per_tile, bw, inv);
+    if (vmax == 1)
+        hipLaunchKernelGGL((k_batch<MODE, 1>), dim3(blocks), dim3(a.cfg.waves_per_block * kWave), 0,
+                           s, (const uint32_t*)a.in, (uint32_t*)a.out, a.table, a.n,
+                           a.arena_words, a.word_bits, (const int64_t*)a.ws, vmax,
+                           a.cfg.rows_per_tile, bw, inv);
+    else
+        hipLaunchKernelGGL((k_batch<MODE, 4>), dim3(blocks), dim3(a.cfg.waves_per_block * kWave), 0,
+                           s, (const uint32_t*)a.in, (uint32_t*)a.out, a.table, a.n,
+                           a.arena_words, a.word_bits, (const int64_t*)a.ws, vmax,
+                           a.cfg.rows_per_tile, bw, inv);
     return launch_status();
 }
 

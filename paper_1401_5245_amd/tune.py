@@ -178,8 +178,10 @@ def tune_image(inp, out, height, width, *, mode="masks", border="white", candida
 
 
 def batch_candidates():
-    for vec, rows, waves, bpc in itertools.product((2, 4), (2, 4, 8, 16, 32), (2, 4, 8),
-                                                   (1, 2, 4, 8, 16)):
+    # vec 1 builds the batch kernel without its wide strip paths (fewer
+    # registers, more wavefronts per compute unit): best for small crops
+    for vec, rows, waves, bpc in itertools.product((1, 4), (2, 4, 8, 16), (1, 2, 4),
+                                                   (4, 8, 16, 24, 32)):
         yield dict(vec_words=vec, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=bpc,
                    cache_policy=1)
 

@@ -190,3 +190,20 @@ def test_invalid_descriptor_is_skipped_on_device():
         if i == 2 or H == 0:
             continue
         assert_same(got, oracle.edge(im), f"image {i}")
+
+
+@pytest.mark.parametrize("word_bits", [32, 64])
+@pytest.mark.parametrize("mode", ["masks", "full"])
+@pytest.mark.parametrize("plan", ["host", "device"])
+def test_narrow_only_kernel_variant(word_bits, mode, plan):
+    """vec_words = 1 selects the batch kernel built without wide strip paths
+    (more wavefronts per compute unit): glyph crops mixed with a few wide
+    images (one-word strips), many persistent workgroups."""
+    from synth import images
+    crops = images.glyph_crops(300, seed=21)
+    imgs = list(crops) + mixed_images(6, seed=22, side=(300, 2500))
+    for rows, bpc in ((4, 8), (8, 24), (1, 32)):
+        cfg = dict(vec_words=1, rows_per_tile=rows, waves_per_block=4, blocks_per_cu=bpc,
+                   cache_policy=1)
+        b = run_batch(imgs, word_bits, mode=mode, cfg=cfg, plan=plan)
+        check_batch(b, imgs, mode=mode)
