@@ -543,64 +543,96 @@ __device__ __forceinline__ void peel_unit(const Geom& g, int64_t chunk, int y0, 
 // Rows [ya, yb) of an image whose rows have g.wd <= 32 words: 64 / wd rows
 // side by side per wavefront step, one word per lane, kNarrowSteps steps
 // loaded before any is used. Lanes past the last row load a safe word and
-// store nothing.
+// store nothing. A group of kNarrowSteps steps is split into its loads
+// (narrow_load) and its arithmetic and stores (narrow_emit), so that a caller
+// can issue the next group's loads before finishing the current one.
+struct NarrowLanes {
+    int wd, grp, q, j;
+    bool used;
+    uint32_t vm, om;
+};
+
+__device__ __forceinline__ NarrowLanes narrow_lanes(const Geom& g, uint32_t bw) {
+    const int lane = threadIdx.x & (kWave - 1);
+    NarrowLanes l;
+    l.wd = g.wd;
+    l.grp = kWave / l.wd;
+    l.q = lane / l.wd;
+    l.used = l.q < l.grp;
+    l.j = l.used ? lane - l.q * l.wd : 0;
+    l.vm = valid_bits(l.j, g.width);
+    l.om = bw & ~l.vm;
+    return l;
+}
+
+struct NarrowGroup {
+    uint32_t c[kNarrowSteps], u[kNarrowSteps], d[kNarrowSteps];
+};
+
+// Loads of the group starting at row y of the unit [ya, yb).
+__device__ __forceinline__ void narrow_load(const Geom& g, const NarrowLanes& l, int ya, int yb,
+                                            int y, NarrowGroup& r) {
+#pragma unroll
+    for (int i = 0; i < kNarrowSteps; ++i) {
+        const int yy = y + i * l.grp + l.q;
+        const bool live = l.used && yy < yb;
+        const int ys = live ? yy : ya;
+        const uint32_t* p = g.in + (int64_t)ys * g.stride + l.j;
+        r.c[i] = p[0];
+        r.u[i] = p[ys > 0 ? -g.stride : 0];
+        r.d[i] = p[ys + 1 < g.height ? g.stride : 0];
+    }
+}
+
+// Edge words of the group starting at row y, from its loaded words.
+template <int MODE>
+__device__ __forceinline__ void narrow_emit(const Geom& g, const NarrowLanes& l, int yb, int y,
+                                            const NarrowGroup& r, uint32_t bw, bool invert) {
+    const int j = l.j, wd = l.wd;
+    const uint32_t vm = l.vm, om = l.om;
+#pragma unroll
+    for (int i = 0; i < kNarrowSteps; ++i) {
+        const int yy = y + i * l.grp + l.q;
+        const bool live = l.used && yy < yb;
+        const uint32_t cc = (r.c[i] & vm) | om;
+        const uint32_t uu = yy > 0 ? ((r.u[i] & vm) | om) : bw;
+        const uint32_t dd = yy + 1 < g.height ? ((r.d[i] & vm) | om) : bw;
+        uint32_t cl = from_lower_lane(cc, bw), cr = from_upper_lane(cc, bw);
+        if (j == 0) cl = bw;
+        if (j == wd - 1) cr = bw;
+        uint32_t ul = bw, ur = bw, dl = bw, dr = bw;
+        if constexpr (MODE == kModeFull || MODE == kModeClause2) {
+            ul = from_lower_lane(uu, bw); ur = from_upper_lane(uu, bw);
+            dl = from_lower_lane(dd, bw); dr = from_upper_lane(dd, bw);
+            if (j == 0) { ul = bw; dl = bw; }
+            if (j == wd - 1) { ur = bw; dr = bw; }
+        }
+        uint32_t* op = g.out + (int64_t)yy * g.stride + j;
+        if constexpr (MODE == kModeDirections) {
+            const uint32_t m = ~cc & vm;
+            if (live) {
+                op[0] = m & west_of(cc, cl);
+                op[g.plane] = m & east_of(cc, cr);
+                op[2 * g.plane] = m & uu;
+                op[3 * g.plane] = m & dd;
+            }
+        } else {
+            const uint32_t v = edge_word<MODE>(cc, east_of(uu, ur), uu, west_of(uu, ul),
+                                               west_of(cc, cl), west_of(dd, dl), dd,
+                                               east_of(dd, dr), east_of(cc, cr)) & vm;
+            if (live) op[0] = invert ? (v ^ vm) : v;
+        }
+    }
+}
+
 template <int MODE>
 __device__ __forceinline__ void narrow_unit(const Geom& g, int ya, int yb, uint32_t bw,
                                             bool invert) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wd = g.wd;
-    const int grp = kWave / wd;
-    const int q = lane / wd;
-    const bool lane_used = q < grp;
-    const int j = lane_used ? lane - q * wd : 0;
-    const uint32_t vm = valid_bits(j, g.width), om = bw & ~vm;
-    constexpr int S = kNarrowSteps;
-
-    for (int y = ya; y < yb; y += grp * S) {
-        uint32_t c[S], u[S], d[S];
-        bool live[S];
-        int yy[S];
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-            yy[i] = y + i * grp + q;
-            live[i] = lane_used && yy[i] < yb;
-            const int ys = live[i] ? yy[i] : ya;
-            const uint32_t* p = g.in + (int64_t)ys * g.stride + j;
-            c[i] = p[0];
-            u[i] = p[ys > 0 ? -g.stride : 0];
-            d[i] = p[ys + 1 < g.height ? g.stride : 0];
-        }
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-            const uint32_t cc = (c[i] & vm) | om;
-            const uint32_t uu = yy[i] > 0 ? ((u[i] & vm) | om) : bw;
-            const uint32_t dd = yy[i] + 1 < g.height ? ((d[i] & vm) | om) : bw;
-            uint32_t cl = from_lower_lane(cc, bw), cr = from_upper_lane(cc, bw);
-            if (j == 0) cl = bw;
-            if (j == wd - 1) cr = bw;
-            uint32_t ul = bw, ur = bw, dl = bw, dr = bw;
-            if constexpr (MODE == kModeFull || MODE == kModeClause2) {
-                ul = from_lower_lane(uu, bw); ur = from_upper_lane(uu, bw);
-                dl = from_lower_lane(dd, bw); dr = from_upper_lane(dd, bw);
-                if (j == 0) { ul = bw; dl = bw; }
-                if (j == wd - 1) { ur = bw; dr = bw; }
-            }
-            uint32_t* op = g.out + (int64_t)yy[i] * g.stride + j;
-            if constexpr (MODE == kModeDirections) {
-                const uint32_t m = ~cc & vm;
-                if (live[i]) {
-                    op[0] = m & west_of(cc, cl);
-                    op[g.plane] = m & east_of(cc, cr);
-                    op[2 * g.plane] = m & uu;
-                    op[3 * g.plane] = m & dd;
-                }
-            } else {
-                const uint32_t v = edge_word<MODE>(cc, east_of(uu, ur), uu, west_of(uu, ul),
-                                                   west_of(cc, cl), west_of(dd, dl), dd,
-                                                   east_of(dd, dr), east_of(cc, cr)) & vm;
-                if (live[i]) op[0] = invert ? (v ^ vm) : v;
-            }
-        }
+    const NarrowLanes l = narrow_lanes(g, bw);
+    for (int y = ya; y < yb; y += l.grp * kNarrowSteps) {
+        NarrowGroup r;
+        narrow_load(g, l, ya, yb, y, r);
+        narrow_emit<MODE>(g, l, yb, y, r, bw, invert);
     }
 }
 

@@ -273,30 +273,48 @@ __global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out
     int i = reinterpret_cast<const int32_t*>(ws + ws_block_map_offset(n))[lb];
     i = i < 0 ? 0 : (i >= n ? n - 1 : i);
     const int per = word_bits / 32;
+    // Geometry of image `cur`, computed once for all of its units in this
+    // range; `first` and `next` are the first units of images i and i + 1.
+    constexpr int64_t kNone = INT64_MAX;
+    int cur = -1;
+    bool ok = false;
+    Geom g;
+    UnitShape s{0, 1, 1, 1, 0};
+    int64_t first = start[i];
+    int64_t next = i + 1 < n ? start[i + 1] : kNone;
     for (int64_t u = u0; u < u1; ++u) {
-        while (i + 1 < n && start[i + 1] <= u) ++i;
-        const edge_image_desc d = tab[i];
-        if (!desc_ok(d, arena_words, word_bits) || d.height == 0 || d.width == 0) continue;
-        const int64_t wd = ((int64_t)d.width + word_bits - 1) / word_bits * per;
-        Geom g;
-        g.in = in + d.offset_words * per;
-        g.out = out + d.offset_words * per;
-        g.stride = d.stride_words * per;
-        g.height = d.height;
-        g.width = d.width;
-        g.wd = (int32_t)wd;
-        g.plane = 0;
-        g.grey = nullptr;
-        g.grey_stride = 0;
-        g.thr = 0;
-        const UnitShape s = unit_shape(d.height, d.width, wd, d.offset_words * per,
-                                       d.stride_words * per, vmax, rows);
-        const int64_t local = u - start[i];
+        while (next <= u) {
+            ++i;
+            first = next;
+            next = i + 1 < n ? start[i + 1] : kNone;
+        }
+        if (i != cur) {
+            cur = i;
+            const edge_image_desc d = tab[i];
+            ok = desc_ok(d, arena_words, word_bits) && d.height > 0 && d.width > 0;
+            if (ok) {
+                const int64_t wd = ((int64_t)d.width + word_bits - 1) / word_bits * per;
+                g.in = in + d.offset_words * per;
+                g.out = out + d.offset_words * per;
+                g.stride = d.stride_words * per;
+                g.height = d.height;
+                g.width = d.width;
+                g.wd = (int32_t)wd;
+                g.plane = 0;
+                g.grey = nullptr;
+                g.grey_stride = 0;
+                g.thr = 0;
+                s = unit_shape(d.height, d.width, wd, d.offset_words * per, d.stride_words * per,
+                               vmax, rows);
+            }
+        }
+        if (!ok) continue;
+        const int64_t local = u - first;
         if (local < 0 || local >= s.count) continue;
-        const int64_t strip = local / s.chunks;
+        const int64_t strip = s.chunks == 1 ? local : local / s.chunks;
         const int64_t chunk = local - strip * s.chunks;
         const int64_t y0 = strip * s.band;
-        const int64_t y1 = y0 + s.band < d.height ? y0 + s.band : d.height;
+        const int64_t y1 = y0 + s.band < g.height ? y0 + s.band : g.height;
         if (s.narrow) {
             narrow_unit<MODE>(g, (int)y0, (int)y1, bw, invert != 0);
         } else if (VMAX >= 4 && s.vw == 4) {
