@@ -455,6 +455,7 @@ def serving(torch, em, p99_bound_ms=20.0, budget=4 << 30):
                      "max_sustained": None if best is None else {
                          "offered_rps": best["offered_rps"], "gpx_s": best["gpx_s"],
                          "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"],
+                         "host_link_gbs_each_way": best["host_link_gbs_each_way"],
                          "stages_p50_p99": best["stages_p50_p99"]}}
     b, p = out["batched"]["max_sustained"], out["per_request"]["max_sustained"]
     if b and p:

@@ -439,14 +439,17 @@ class Server:
         d2h = np.array([(r.done - (r.kernel_done if r.kernel_done >= 0 else r.done)) * 1e3
                         for r in served])
         pixels = int(sum(int(pool.pixels[r.pool_index]) for r in served))
+        copied = int(sum(int(words[r.rid]) for r in served)) * self.word_bytes   # each way
         t_first = min((r.arrival for r in served), default=0.0)
         t_last = max((r.done for r in served), default=0.0)
         pct = (lambda a, p: round(float(np.percentile(a, p)), 3) if a.size else None)
         stages = {"launch_to_kernel_done_ms": [pct(k_seen, 50), pct(k_seen, 99)],
                   "copy_out_ms": [pct(d2h, 50), pct(d2h, 99)],
                   "queue_ms": [pct(queue, 50), pct(queue, 99)]}
-        st = Stats(lat, lat_k, queue, pixels, t_last - t_first, nbatches, rejected,
+        dur = t_last - t_first
+        st = Stats(lat, lat_k, queue, pixels, dur, nbatches, rejected,
                    {"stages_p50_p99": stages,
+                    "host_link_gbs_each_way": round(copied / dur / 1e9, 2) if dur > 0 else 0.0,
                     "max_loop_pass_ms": round(max_pass * 1e3, 3),
                     "max_oversleep_ms": round(max_oversleep * 1e3, 3),
                     "host_stalls_over_1ms": int(stalls_over_1ms),
