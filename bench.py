@@ -403,6 +403,38 @@ def batched_crops(torch, em, tm, steps):
             "bit_exact_first_256": exact}
 
 
+def host_link_ceiling(torch, nbytes=256 << 20, reps=5):
+    """GB/s of pinned host <-> device copies on the serving path's copy call
+    (hipMemcpyAsync): host to device, device to host, and both at once on
+    two streams (each way)."""
+    from paper_1401_5245_amd.serve import _copy_async
+    n = nbytes // 8
+    host_a = torch.empty(n, dtype=torch.int64).pin_memory()
+    host_b = torch.empty(n, dtype=torch.int64).pin_memory()
+    dev_a = torch.empty(n, dtype=torch.int64, device="cuda")
+    dev_b = torch.empty(n, dtype=torch.int64, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    h2d = timed(lambda: _copy_async(dev_a, 0, host_a, 0, n, s1))
+    d2h = timed(lambda: _copy_async(host_b, 0, dev_b, 0, n, s2))
+    both = timed(lambda: (_copy_async(dev_a, 0, host_a, 0, n, s1),
+                          _copy_async(host_b, 0, dev_b, 0, n, s2)))
+    del host_a, host_b, dev_a, dev_b
+    torch.cuda.empty_cache()
+    return {"h2d_gbs": round(nbytes / h2d / 1e9, 1), "d2h_gbs": round(nbytes / d2h / 1e9, 1),
+            "both_each_way_gbs": round(nbytes / both / 1e9, 1),
+            "note": "256 MiB pinned copies with hipMemcpyAsync, host-timed"}
+
+
 def serving(torch, em, p99_bound_ms=20.0, budget=4 << 30):
     """Poisson request stream over a 64-image pool (sides log-uniform in
     [64, 4096], half glyph pages, half Bernoulli(0.3)); sweep the offered
@@ -457,6 +489,8 @@ def serving(torch, em, p99_bound_ms=20.0, budget=4 << 30):
                          "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"],
                          "host_link_gbs_each_way": best["host_link_gbs_each_way"],
                          "stages_p50_p99": best["stages_p50_p99"]}}
+    out["host_link_ceiling"] = host_link_ceiling(torch)
+    log(f"host link: {out['host_link_ceiling']}")
     b, p = out["batched"]["max_sustained"], out["per_request"]["max_sustained"]
     if b and p:
         out["speedup_at_p99_bound"] = round(b["gpx_s"] / p["gpx_s"], 2)

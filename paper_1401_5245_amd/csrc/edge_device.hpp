@@ -569,18 +569,24 @@ struct NarrowGroup {
     uint32_t c[kNarrowSteps], u[kNarrowSteps], d[kNarrowSteps];
 };
 
-// Loads of the group starting at row y of the unit [ya, yb).
+// Loads of the group starting at row y of the unit [ya, yb). Each lane's
+// row pointer is formed once and advanced by grp rows per step; lanes past
+// the unit's last row read row ya instead.
 __device__ __forceinline__ void narrow_load(const Geom& g, const NarrowLanes& l, int ya, int yb,
                                             int y, NarrowGroup& r) {
+    const int64_t step = (int64_t)l.grp * g.stride;
+    const uint32_t* row = g.in + (int64_t)(y + l.q) * g.stride + l.j;
+    const uint32_t* safe = g.in + (int64_t)ya * g.stride + l.j;
 #pragma unroll
     for (int i = 0; i < kNarrowSteps; ++i) {
         const int yy = y + i * l.grp + l.q;
         const bool live = l.used && yy < yb;
         const int ys = live ? yy : ya;
-        const uint32_t* p = g.in + (int64_t)ys * g.stride + l.j;
+        const uint32_t* p = live ? row : safe;
         r.c[i] = p[0];
         r.u[i] = p[ys > 0 ? -g.stride : 0];
         r.d[i] = p[ys + 1 < g.height ? g.stride : 0];
+        row += step;
     }
 }
 
@@ -590,6 +596,8 @@ __device__ __forceinline__ void narrow_emit(const Geom& g, const NarrowLanes& l,
                                             const NarrowGroup& r, uint32_t bw, bool invert) {
     const int j = l.j, wd = l.wd;
     const uint32_t vm = l.vm, om = l.om;
+    const int64_t step = (int64_t)l.grp * g.stride;
+    uint32_t* row = g.out + (int64_t)(y + l.q) * g.stride + j;
 #pragma unroll
     for (int i = 0; i < kNarrowSteps; ++i) {
         const int yy = y + i * l.grp + l.q;
@@ -607,7 +615,8 @@ __device__ __forceinline__ void narrow_emit(const Geom& g, const NarrowLanes& l,
             if (j == 0) { ul = bw; dl = bw; }
             if (j == wd - 1) { ur = bw; dr = bw; }
         }
-        uint32_t* op = g.out + (int64_t)yy * g.stride + j;
+        uint32_t* op = row;                       // row yy of this lane
+        row += step;
         if constexpr (MODE == kModeDirections) {
             const uint32_t m = ~cc & vm;
             if (live) {
