@@ -538,6 +538,97 @@ __device__ __forceinline__ void peel_unit(const Geom& g, int64_t chunk, int y0, 
         if (t + u <= tlast) step(t + u, q[u]);
 }
 
+// Peeling with the levels of one strip split over two wavefronts of a
+// workgroup (twice the wavefronts for the same halo rows, half the
+// registers each). Wavefront 0 loads the rows and forms levels 1..LA for a
+// group of P steps, writing each step's top row (level LA) to LDS; after
+// the workgroup barrier wavefront 1 forms levels LA+1..LA+LB from those P
+// rows while wavefront 0 goes on with the next group. The LDS ring holds two
+// groups: a group's rows are overwritten two groups later, after wavefront 1
+// has passed the barrier that follows its reading them. Both wavefronts run
+// the same groups, one barrier each, so the barrier count always matches.
+// The stored words equal those of peel_unit<LA + LB, ...>.
+constexpr int kPeelSplitGroup = 3;
+
+template <int LA, int LB, bool EDGEOUT, class Pol>
+__device__ __forceinline__ void peel_split_unit(const Geom& g, int64_t chunk, int y0, int y1,
+                                                uint32_t bw, int role,
+                                                uint32_t (*lds)[kWave]) {
+    static_assert(LA >= 1 && LB >= 1 && LA + LB <= 31, "the halo lanes carry 32 pixels");
+    constexpr int L = LA + LB;
+    constexpr int P = kPeelSplitGroup;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t j = chunk * kPeelSpan - 1 + lane;
+    const bool inrow = j >= 0 && j < g.wd;
+    const bool keep = inrow && lane >= 1 && lane <= kWave - 2;
+    const uint32_t vm = inrow ? valid_bits((int)j, g.width) : 0u;
+    const uint32_t om = bw & ~vm;
+    const int64_t jl = inrow ? j : (j < 0 ? 0 : (int64_t)g.wd - 1);
+
+    auto load = [&](int y) -> uint32_t {
+        const int yc = y < 0 ? 0 : (y >= g.height ? g.height - 1 : y);
+        const uint32_t* p = g.in + (int64_t)yc * g.stride + jl;
+        return Pol::nt_load ? __builtin_nontemporal_load(p) : *p;
+    };
+
+    constexpr int LM = LA > LB ? LA : LB;
+    uint32_t A[LM], B[LM];
+#pragma unroll
+    for (int i = 0; i < LM; ++i) { A[i] = bw; B[i] = bw; }
+
+    // C levels of this wavefront's part, fed with row n
+    auto levels = [&](uint32_t n, auto count_tag) -> uint32_t {
+        constexpr int C = decltype(count_tag)::value;
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const uint32_t c = B[i];
+            const uint32_t lw = from_lower_lane0(c), le = from_upper_lane0(c);
+            const uint32_t v = (c | west_of(c, lw) | east_of(c, le)) | (A[i] | n);
+            A[i] = c;
+            B[i] = n;
+            n = v;
+        }
+        return n;
+    };
+
+    auto finish = [&](int t, uint32_t n) {     // n = L_L(t - L); A[LB-1] = L_{L-1}(t - L)
+        const int y = t - L;
+        if (y >= y0 && keep) {
+            const uint32_t res = (EDGEOUT ? (n & ~A[LB - 1]) : n) & vm;
+            uint32_t* op = g.out + (int64_t)y * g.stride + j;
+            if constexpr (Pol::nt_store) __builtin_nontemporal_store(res, op);
+            else *op = res;
+        }
+    };
+
+    const int t0 = y0 - L, tlast = y1 - 1 + L;
+    uint32_t q[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) q[u] = role == 0 ? load(min(t0 + u, tlast)) : 0u;
+    int half = 0;
+    for (int t = t0; t <= tlast; t += P, half ^= 1) {
+        if (role == 0) {
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const int tt = t + u;
+                const uint32_t raw = q[u];
+                q[u] = load(min(tt + P, tlast));
+                const uint32_t n0 = (unsigned)tt < (unsigned)g.height ? ((raw & vm) | om) : bw;
+                if (tt <= tlast) lds[half * P + u][lane] = levels(n0, std::integral_constant<int, LA>{});
+            }
+        }
+        __syncthreads();
+        if (role == 1) {
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const int tt = t + u;
+                if (tt <= tlast)
+                    finish(tt, levels(lds[half * P + u][lane], std::integral_constant<int, LB>{}));
+            }
+        }
+    }
+}
+
 // --------------------------------------------------------- narrow units ----
 
 // Rows [ya, yb) of an image whose rows have g.wd <= 32 words: 64 / wd rows

@@ -70,6 +70,22 @@ __global__ void __launch_bounds__(512) k_peel(Geom g, int64_t chunks, int rows, 
     peel_unit<L, EDGEOUT, COPY, Pol>(g, chunk, (int)y0, (int)y1, bw);
 }
 
+// Iterated peeling with a strip's levels split over the two wavefronts of
+// a workgroup (one strip per workgroup, so both leave together).
+template <int LA, int LB, bool EDGEOUT>
+__global__ void __launch_bounds__(2 * kWave) k_peel_split(Geom g, int64_t chunks, int rows,
+                                                         int64_t nunits, uint32_t bw) {
+    __shared__ uint32_t xfer[2 * kPeelSplitGroup][kWave];
+    const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x);
+    if (unit >= nunits) return;
+    const int role = wave_uniform(threadIdx.x / kWave);
+    const int64_t strip = unit / chunks;
+    const int64_t chunk = unit - strip * chunks;
+    const int64_t y0 = strip * rows;
+    const int64_t y1 = y0 + rows < g.height ? y0 + rows : g.height;
+    peel_split_unit<LA, LB, EDGEOUT, CachedStrip>(g, chunk, (int)y0, (int)y1, bw, role, xfer);
+}
+
 // One image with rows of <= 32 words, `band` rows per wavefront.
 template <int MODE>
 __global__ void __launch_bounds__(512) k_narrow(Geom g, int64_t band, int64_t nunits, uint32_t bw,
@@ -817,6 +833,20 @@ int launch_peel_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, hip
     return launch_status();
 }
 
+// From this many levels a strip's levels are split over two wavefronts.
+constexpr int kPeelSplitLevels = 16;
+
+template <int L, bool EDGEOUT>
+int launch_peel_split_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t bw,
+                             hipStream_t s) {
+    const int64_t chunks = ceil_div(g.wd, (int64_t)kPeelSpan);
+    const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
+    if (!grid_fits(nunits, 2 * kWave)) return EDGE_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL((k_peel_split<L / 2, L - L / 2, EDGEOUT>), dim3((uint32_t)nunits),
+                       dim3(2 * kWave), 0, s, g, chunks, c.rows_per_tile, nunits, bw);
+    return launch_status();
+}
+
 // One instantiation per level count 1..31 (levels are a template constant
 // so that every level's rows stay in registers).
 template <int L, bool EDGEOUT>
@@ -824,18 +854,24 @@ int launch_peel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int levels
     if constexpr (L > 31) {
         return EDGE_ERR_INVALID;
     } else {
-        if (levels == L) return launch_peel_kernel<L, EDGEOUT, false>(g, c, bw, s);
+        if (levels == L) {
+            if constexpr (L >= kPeelSplitLevels)
+                return launch_peel_split_kernel<L, EDGEOUT>(g, c, bw, s);
+            else
+                return launch_peel_kernel<L, EDGEOUT, false>(g, c, bw, s);
+        }
         return launch_peel<L + 1, EDGEOUT>(g, c, bw, levels, s);
     }
 }
 
-// Built-in peel shape, from a sweep at 8192^2 and 16384^2: a unit
+// Built-in peel shape, from sweeps at 8192^2 and 16384^2: a unit
 // recomputes 2 * iterations halo rows, so strips are about twice as tall as
 // the iteration count (at least 8, at most 64 rows), doubled once when the
-// image would still give more than 8192 strips; 4 wavefronts per workgroup.
-// cache_policy is not used: peel units load through the caches, which keep
-// the halo rows that neighbouring strips share.
-edge_launch_cfg default_peel(int64_t height, int64_t wd32, int iterations) {
+// image would still give more than 8192 strips (4096 when each strip takes
+// two wavefronts); 4 wavefronts per workgroup. cache_policy is not used:
+// peel units load through the caches, which keep the halo rows that
+// neighbouring strips share.
+edge_launch_cfg default_peel(int64_t height, int64_t wd32, int iterations, int levels) {
     edge_launch_cfg c;
     c.vec_words = 1;
     c.blocks_per_cu = 1;
@@ -844,9 +880,11 @@ edge_launch_cfg default_peel(int64_t height, int64_t wd32, int iterations) {
     const int64_t chunks = ceil_div(wd32, (int64_t)kPeelSpan);
     int64_t rows = 8;
     while (rows < 2 * iterations && rows < 64) rows *= 2;
-    if (rows < 64 && chunks * ceil_div(height, rows) > 8192) rows *= 2;
-    // keep the grid (one wavefront per strip) within 2^32 work-items
-    while (chunks * ceil_div(height, rows) >= (1ll << 26) && rows < 1024) rows *= 2;
+    const int64_t many = levels >= kPeelSplitLevels ? 4096 : 8192;
+    if (rows < 64 && chunks * ceil_div(height, rows) > many) rows *= 2;
+    // keep the grid (one or two wavefronts per strip) within 2^32 work-items
+    const int64_t max_units = levels >= kPeelSplitLevels ? (1ll << 25) : (1ll << 26);
+    while (chunks * ceil_div(height, rows) >= max_units && rows < 1024) rows *= 2;
     c.rows_per_tile = (int32_t)rows;
     return c;
 }
@@ -1040,7 +1078,8 @@ int edge_peel(const void* in, void* out, int64_t height, int64_t width, int64_t 
     g.grey = nullptr;
     g.grey_stride = 0;
     g.thr = 0;
-    const edge_launch_cfg c = cfg ? *cfg : default_peel(height, g.wd, iterations);
+    const int levels = iterations + ((flags & EDGE_FLAG_PEEL_EDGE) ? 1 : 0);
+    const edge_launch_cfg c = cfg ? *cfg : default_peel(height, g.wd, iterations, levels);
     const uint32_t bw = border_word(border);
     hipStream_t s = (hipStream_t)hip_stream;
     if (flags & EDGE_FLAG_PEEL_EDGE) return launch_peel<1, true>(g, c, bw, iterations + 1, s);

@@ -15,6 +15,7 @@ from tests.gpu_util import assert_same, log
 pytestmark = pytest.mark.gpu
 
 PEELS = 3
+DEEP = 20          # levels split over two wavefronts per strip
 
 
 def random_words(shape):
@@ -27,12 +28,14 @@ def run_all(inp, H, W):
     """Plain, full definition and peel (image and layer) of one image."""
     import paper_1401_5245_amd as em
     outs = {}
-    for name in ("plain", "full", "peel", "layer"):
+    for name in ("plain", "full", "peel", "layer", "deep"):
         out = torch.empty_like(inp)
         if name == "plain":
             em.edge_masks(inp, out, H, W)
         elif name == "full":
             em.edge_full(inp, out, H, W)
+        elif name == "deep":
+            em.peel(inp, out, H, W, DEEP)
         else:
             em.peel(inp, out, H, W, PEELS, edge_out=name == "layer")
         outs[name] = out
@@ -45,6 +48,8 @@ def oracle_of(name, win):
         return oracle.edge(win)
     if name == "full":
         return oracle.edge(win, clauses=oracle.CLAUSE1 | oracle.CLAUSE2)
+    if name == "deep":
+        return oracle.peel(win, DEEP)
     return oracle.peel(win, PEELS, edge_out=name == "layer")
 
 
@@ -69,7 +74,7 @@ def test_tallest_image():
     log(f"tallest image: {H} x {W}")
     inp = random_words((H, 1))
     outs = run_all(inp, H, W)
-    m = PEELS + 2
+    m = DEEP + 2
     for y in (0, 1, 2, H // 2, H - 3, H - 2, H - 1):
         lo, hi = max(0, y - m), min(H, y + m + 1)
         win = unpack_rows(inp[lo:hi].cpu().numpy().view(np.uint64), W)
