@@ -868,12 +868,26 @@ SECTIONS = {
 }
 
 
+def device_clock_mhz(attr: int):
+    """Peak clock of device 0 in MHz from hipDeviceGetAttribute (attribute 5:
+    engine clock, 60: memory clock; both reported in kHz), None if unknown."""
+    import ctypes
+    try:
+        lib = ctypes.CDLL("libamdhip64.so")
+        v = ctypes.c_int(0)
+        if lib.hipDeviceGetAttribute(ctypes.byref(v), ctypes.c_int(attr), ctypes.c_int(0)) != 0:
+            return None
+        return v.value // 1000 or None
+    except OSError:
+        return None
+
+
 def versions(torch) -> dict:
     p = torch.cuda.get_device_properties(0)
     return {"torch": torch.__version__, "hip": torch.version.hip, "device": p.name,
             "arch": getattr(p, "gcnArchName", "?"), "compute_units": p.multi_processor_count,
             "hbm_gib": round(p.total_memory / 2**30, 1),
-            "clock_mhz": getattr(p, "clock_rate", 0) // 1000 or None}
+            "clock_mhz": device_clock_mhz(5), "memory_clock_mhz": device_clock_mhz(60)}
 
 
 def main():

@@ -842,7 +842,8 @@ int launch_peel_split_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t b
     const int64_t chunks = ceil_div(g.wd, (int64_t)kPeelSpan);
     const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
     if (!grid_fits(nunits, 2 * kWave)) return EDGE_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL((k_peel_split<L / 2, L - L / 2, EDGEOUT>), dim3((uint32_t)nunits),
+    constexpr int LA = peel_split_first(L);
+    hipLaunchKernelGGL((k_peel_split<LA, L - LA, EDGEOUT>), dim3((uint32_t)nunits),
                        dim3(2 * kWave), 0, s, g, chunks, c.rows_per_tile, nunits, bw);
     return launch_status();
 }
@@ -864,14 +865,15 @@ int launch_peel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int levels
     }
 }
 
-// Built-in peel shape, from sweeps at 8192^2 and 16384^2: a unit
-// recomputes 2 * iterations halo rows, so strips are about twice as tall as
-// the iteration count (at least 8, at most 64 rows), doubled once when the
-// image would still give more than 8192 strips (4096 when each strip takes
-// two wavefronts); 4 wavefronts per workgroup. cache_policy is not used:
-// peel units load through the caches, which keep the halo rows that
+// Built-in peel shape, from sweeps at 8192^2 and 16384^2: a unit walks
+// 2 * levels halo rows besides its strip (the first half of them with few
+// levels formed), so strips are the smallest power of two above the level
+// count (at least 8, at most 64 rows), doubled once when the image would
+// still give more than 8192 strips (4096 when each strip takes two
+// wavefronts); 4 wavefronts per workgroup. cache_policy is not used: peel
+// units load through the caches, which keep the halo rows that
 // neighbouring strips share.
-edge_launch_cfg default_peel(int64_t height, int64_t wd32, int iterations, int levels) {
+edge_launch_cfg default_peel(int64_t height, int64_t wd32, int levels) {
     edge_launch_cfg c;
     c.vec_words = 1;
     c.blocks_per_cu = 1;
@@ -879,7 +881,7 @@ edge_launch_cfg default_peel(int64_t height, int64_t wd32, int iterations, int l
     c.waves_per_block = 4;
     const int64_t chunks = ceil_div(wd32, (int64_t)kPeelSpan);
     int64_t rows = 8;
-    while (rows < 2 * iterations && rows < 64) rows *= 2;
+    while (rows <= levels && rows < 64) rows *= 2;
     const int64_t many = levels >= kPeelSplitLevels ? 4096 : 8192;
     if (rows < 64 && chunks * ceil_div(height, rows) > many) rows *= 2;
     // keep the grid (one or two wavefronts per strip) within 2^32 work-items
@@ -1079,7 +1081,7 @@ int edge_peel(const void* in, void* out, int64_t height, int64_t width, int64_t 
     g.grey_stride = 0;
     g.thr = 0;
     const int levels = iterations + ((flags & EDGE_FLAG_PEEL_EDGE) ? 1 : 0);
-    const edge_launch_cfg c = cfg ? *cfg : default_peel(height, g.wd, iterations, levels);
+    const edge_launch_cfg c = cfg ? *cfg : default_peel(height, g.wd, levels);
     const uint32_t bw = border_word(border);
     hipStream_t s = (hipStream_t)hip_stream;
     if (flags & EDGE_FLAG_PEEL_EDGE) return launch_peel<1, true>(g, c, bw, iterations + 1, s);

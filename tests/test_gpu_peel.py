@@ -132,3 +132,34 @@ def test_peel_composes():
         em.peel(b, c, H, W, 7, border=border)
         torch.cuda.synchronize()
         assert torch.equal(a, c), f"5 then 7 != 12 ({border})"
+
+
+def white_seeds(H, W, n, seed):
+    """A black image with n isolated white pixels. Each peel grows their
+    diamonds by one pixel, so every level up to 30 still changes rows near
+    them; on images whose deep levels have turned all white, a level formed
+    wrongly (or not at all) would not show."""
+    rng = np.random.default_rng(seed)
+    img = np.zeros((H, W), np.uint8)
+    img[rng.integers(0, H, n), rng.integers(0, W, n)] = 1
+    return img
+
+
+@pytest.mark.parametrize("k", [6, 7, 14, 15, 16, 17, 22, 29, 30])
+def test_peel_deep_levels(k):
+    """Levels that are still changing at every depth, through both the
+    one-wavefront and the split strip units, with strips short enough that
+    every strip starts in a different phase of the level switch-on."""
+    for (H, W, n, wb) in ((90, 3000, 6, 32), (130, 200, 3, 64)):
+        img = white_seeds(H, W, n, seed=H + k)
+        for border in ("black", "white"):
+            for edge_out in (False, True):
+                want = oracle.peel(img, k, border=border, edge_out=edge_out)
+                prev = oracle.peel(img, k - 1, border=border, edge_out=edge_out)
+                assert not np.array_equal(want, prev), "the input does not exercise level k"
+                for rows in (None, 3, 7, 32, 64):
+                    cfg = None if rows is None else dict(
+                        vec_words=1, rows_per_tile=rows, waves_per_block=2, blocks_per_cu=1,
+                        cache_policy=0)
+                    got = run_peel(img, wb, k, border=border, edge_out=edge_out, cfg=cfg)
+                    assert_same(got, want, f"{H}x{W} k={k} {border} edge_out={edge_out} rows={rows}")
