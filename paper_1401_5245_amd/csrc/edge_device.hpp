@@ -24,6 +24,9 @@
 //     wavefront's span are loaded by lanes 0 and 63.
 //   - narrow unit (rows of <= 32 words): several whole rows side by side in
 //     one wavefront, one word per lane, rows above and below read directly.
+//   - peel unit (iterated peeling, below): a strip of one word per lane
+//     with the rows of every peel level in registers; from 16 levels the
+//     levels of one strip are shared by two wavefronts of a workgroup.
 #pragma once
 
 #include <hip/hip_runtime.h>

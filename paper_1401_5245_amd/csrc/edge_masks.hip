@@ -778,10 +778,6 @@ struct EdgeGraph {
     hipGraphExec_t exec;
 };
 
-}  // namespace
-
-namespace {
-
 template <int MODE, class Pol, bool TAIL>
 int launch_grey_part(const Geom& g, const edge_launch_cfg& c, int64_t chunk0, int64_t chunks,
                      uint32_t bw, int invert, hipStream_t stream) {
@@ -816,10 +812,6 @@ int launch_grey_mode(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int i
     if (stream_mode) return launch_grey<MODE, StreamingStrip>(g, c, bw, invert, vec, stream);
     return launch_grey<MODE, CachedStrip>(g, c, bw, invert, vec, stream);
 }
-
-}  // namespace
-
-namespace {
 
 template <int L, bool EDGEOUT, bool COPY>
 int launch_peel_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, hipStream_t s) {
