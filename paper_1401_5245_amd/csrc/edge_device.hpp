@@ -45,7 +45,11 @@ constexpr int kNarrowMaxWords = 32;
 
 // kModeDirections writes the four fundamental edges of section 4 (left,
 // right, up, down: the edge types of Fig. 2) to four output planes.
-enum { kModePlain = 0, kModeFull = 1, kModeClause2 = 2, kModeDirections = 3 };
+// kModePeel writes the image after one peel (its edge points turned white)
+// and kModeCopy the image itself: the single-level cases of iterated
+// peeling, which run the strip loop of the edge kernels.
+enum { kModePlain = 0, kModeFull = 1, kModeClause2 = 2, kModeDirections = 3, kModePeel = 4,
+       kModeCopy = 5 };
 
 // Compile-time choices of the strip loop: rows kept in flight per lane, and
 // non-temporal (streaming) cache policy for the row loads and stores.
@@ -159,6 +163,10 @@ __device__ __forceinline__ uint32_t edge_word(uint32_t c, uint32_t n1, uint32_t 
     const uint32_t white4 = n2 | n4 | n6 | n8;                 // section 1, Edge(p)
     if constexpr (MODE == kModePlain) {
         return ~c & white4;
+    } else if constexpr (MODE == kModePeel) {
+        return c | white4;                                      // c | Edge(c)
+    } else if constexpr (MODE == kModeCopy) {
+        return c;
     } else {
         const uint32_t few = at_most_one_black(n1, n2, n3, n4, n5, n6, n7, n8);
         if constexpr (MODE == kModeFull) return ~c & (white4 | few);
@@ -171,10 +179,13 @@ __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_rea
 // Spread consecutive workgroups over the eight XCDs in contiguous ranges:
 // the dispatcher sends workgroup b to XCD b % 8, so logical block order
 // b' keeps neighbouring tiles (which share halo rows) in one XCD's L2.
+// XCD x takes the q + (x < rem) consecutive logical blocks from
+// x * q + min(x, rem); written without a branch, so that the kernel's
+// argument loads are issued together.
 __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
     constexpr uint32_t X = 8;
     const uint32_t xcd = b % X, idx = b / X, q = nb / X, rem = nb % X;
-    return xcd < rem ? xcd * (q + 1) + idx : rem * (q + 1) + (xcd - rem) * q + idx;
+    return xcd * q + (xcd < rem ? xcd : rem) + idx;
 }
 
 template <int VW, bool NT>
@@ -469,7 +480,7 @@ __device__ __forceinline__ void strip_unit(const Geom& g, int j0, int y0, int y1
 // neighbouring lanes by DPP): six VALU operations per word and level. It is
 // formed at the step where level 0 reaches row r + j; each level keeps its
 // two most recent rows. EDGEOUT stores L_L & ~L_{L-1}, the edge map of the
-// image after L - 1 peels; COPY (L = 1 only) stores the input unchanged.
+// image after L - 1 peels.
 constexpr int kPeelSpan = kWave - 2;
 
 // Warm-up. A strip's walk starts at t0 = y0 - L, and level j first reaches
@@ -505,11 +516,10 @@ __device__ __forceinline__ void peel_phase(int act, F&& f) {
     }
 }
 
-template <int L, bool EDGEOUT, bool COPY, class Pol>
+template <int L, bool EDGEOUT, class Pol>
 __device__ __forceinline__ void peel_unit(const Geom& g, int64_t chunk, int y0, int y1,
                                           uint32_t bw) {
     static_assert(L >= 1 && L <= 31, "the halo lanes carry 32 pixels");
-    static_assert(!COPY || (L == 1 && !EDGEOUT), "COPY is the zero-peel case");
     // three rows in flight: each level's rows rotate through three
     // registers, so a loop body of three steps needs no register moves
     constexpr int P = 3;
@@ -540,7 +550,7 @@ __device__ __forceinline__ void peel_unit(const Geom& g, int64_t chunk, int y0, 
             // level i + 1 at row t - i - 1 from level i rows t-i-2, t-i-1, t-i
             const uint32_t c = B[i];
             uint32_t v = c;
-            if (!COPY && i < ACT) {
+            if (i < ACT) {
                 const uint32_t lw = from_lower_lane0(c), le = from_upper_lane0(c);
                 v = (c | west_of(c, lw) | east_of(c, le)) | (A[i] | n);
             }
@@ -572,7 +582,7 @@ __device__ __forceinline__ void peel_unit(const Geom& g, int64_t chunk, int y0, 
     };
     constexpr auto all = std::integral_constant<int, L>{};
     int t = t0;
-    if constexpr (!COPY && L > kPeelPhase) {
+    if constexpr (L > kPeelPhase) {
         for (; t - t0 < 2 * L && t + P <= tlast + 1; t += P)
             peel_phase<L>(peel_formed(t - t0, P, 0, L), [&](auto a) { group(a, t); });
     }

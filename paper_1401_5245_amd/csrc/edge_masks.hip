@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(512) k_strip_grey(Geom g, int64_t chunk0, int6
 
 // Iterated peeling of one image: strips of `rows` rows x kPeelSpan words,
 // one wavefront per strip, L levels.
-template <int L, bool EDGEOUT, bool COPY, class Pol>
+template <int L, bool EDGEOUT, class Pol>
 __global__ void __launch_bounds__(512) k_peel(Geom g, int64_t chunks, int rows, int64_t nunits,
                                               uint32_t bw) {
     const int wpb = blockDim.x / kWave;
@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(512) k_peel(Geom g, int64_t chunks, int rows, 
     const int64_t chunk = unit - strip * chunks;
     const int64_t y0 = strip * rows;
     const int64_t y1 = y0 + rows < g.height ? y0 + rows : g.height;
-    peel_unit<L, EDGEOUT, COPY, Pol>(g, chunk, (int)y0, (int)y1, bw);
+    peel_unit<L, EDGEOUT, Pol>(g, chunk, (int)y0, (int)y1, bw);
 }
 
 // Iterated peeling with a strip's levels split over the two wavefronts of
@@ -813,13 +813,13 @@ int launch_grey_mode(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int i
     return launch_grey<MODE, CachedStrip>(g, c, bw, invert, vec, stream);
 }
 
-template <int L, bool EDGEOUT, bool COPY>
+template <int L, bool EDGEOUT>
 int launch_peel_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, hipStream_t s) {
     const int64_t chunks = ceil_div(g.wd, (int64_t)kPeelSpan);
     const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
     const int64_t blocks = ceil_div(nunits, c.waves_per_block);
     if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL((k_peel<L, EDGEOUT, COPY, CachedStrip>), dim3((uint32_t)blocks),
+    hipLaunchKernelGGL((k_peel<L, EDGEOUT, CachedStrip>), dim3((uint32_t)blocks),
                        dim3(c.waves_per_block * kWave), 0, s, g, chunks, c.rows_per_tile, nunits,
                        bw);
     return launch_status();
@@ -840,7 +840,7 @@ int launch_peel_split_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t b
     return launch_status();
 }
 
-// One instantiation per level count 1..31 (levels are a template constant
+// One instantiation per level count 2..31 (levels are a template constant
 // so that every level's rows stay in registers).
 template <int L, bool EDGEOUT>
 int launch_peel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int levels, hipStream_t s) {
@@ -851,7 +851,7 @@ int launch_peel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int levels
             if constexpr (L >= kPeelSplitLevels)
                 return launch_peel_split_kernel<L, EDGEOUT>(g, c, bw, s);
             else
-                return launch_peel_kernel<L, EDGEOUT, false>(g, c, bw, s);
+                return launch_peel_kernel<L, EDGEOUT>(g, c, bw, s);
         }
         return launch_peel<L + 1, EDGEOUT>(g, c, bw, levels, s);
     }
@@ -1072,13 +1072,23 @@ int edge_peel(const void* in, void* out, int64_t height, int64_t width, int64_t 
     g.grey = nullptr;
     g.grey_stride = 0;
     g.thr = 0;
-    const int levels = iterations + ((flags & EDGE_FLAG_PEEL_EDGE) ? 1 : 0);
-    const edge_launch_cfg c = cfg ? *cfg : default_peel(height, g.wd, levels);
+    const bool edge_out = (flags & EDGE_FLAG_PEEL_EDGE) != 0;
+    const int levels = iterations + (edge_out ? 1 : 0);
     const uint32_t bw = border_word(border);
     hipStream_t s = (hipStream_t)hip_stream;
-    if (flags & EDGE_FLAG_PEEL_EDGE) return launch_peel<1, true>(g, c, bw, iterations + 1, s);
-    if (iterations == 0) return launch_peel_kernel<1, false, true>(g, c, bw, s);
-    return launch_peel<1, false>(g, c, bw, iterations, s);
+    if (levels <= 1) {
+        // One level (one peel, or the edge map of the image) or none: the
+        // strip loop of the single-image kernels with that word function.
+        const edge_launch_cfg c = cfg ? *cfg : default_single(height, g.wd);
+        int vmax = std::min(c.vec_words, std::min(alignment_words(pin), alignment_words(pout)));
+        const int vw = pick_vw(g.wd, vmax, 0, g.stride);
+        if (levels == 0) return launch_single<kModeCopy>(g, vw, c, bw, 0, s);
+        if (edge_out) return launch_single<kModePlain>(g, vw, c, bw, 0, s);
+        return launch_single<kModePeel>(g, vw, c, bw, 0, s);
+    }
+    const edge_launch_cfg c = cfg ? *cfg : default_peel(height, g.wd, levels);
+    if (edge_out) return launch_peel<2, true>(g, c, bw, levels, s);
+    return launch_peel<2, false>(g, c, bw, levels, s);
 }
 
 int edge_masks_staged(const void* in, void* out, void* scratch, int64_t scratch_bytes,
