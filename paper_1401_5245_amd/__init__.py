@@ -186,6 +186,8 @@ def edge_masks_staged(inp: torch.Tensor, out: torch.Tensor, height: int, width: 
     """The paper's three stages as eight separate passes (the unfused
     ablation of edge_masks; same output)."""
     wb, s = _image_args(inp, out, height, width, stride_words)
+    if not scratch.is_cuda or not scratch.is_contiguous():
+        raise ValueError("scratch must be a contiguous device tensor")
     check(_lib.edge_masks_staged(inp.data_ptr(), out.data_ptr(), scratch.data_ptr(),
                                  scratch.numel() * scratch.element_size(), height, width, s, wb,
                                  BORDERS[border], stream_handle(stream)))
@@ -222,6 +224,10 @@ def prepare(inp: torch.Tensor, out: torch.Tensor, height: int, width: int, *,
 
 def copy_bytes(src: torch.Tensor, dst: torch.Tensor, n_bytes: int, stream=None) -> None:
     """Plain 128-bit device copy (the bandwidth reference for the kernels)."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("source and destination must be contiguous device tensors")
+    if n_bytes > min(src.numel() * src.element_size(), dst.numel() * dst.element_size()):
+        raise ValueError(f"{n_bytes} bytes exceed the source or destination tensor")
     check(_lib.edge_copy_bytes(src.data_ptr(), dst.data_ptr(), n_bytes, stream_handle(stream)))
 
 

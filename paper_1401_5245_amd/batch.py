@@ -119,6 +119,20 @@ def plan_batch(in_arena: torch.Tensor, out_arena: torch.Tensor, table: np.ndarra
     return out, int(used.value)
 
 
+def _check_batch_tensors(in_arena, out_arena, table_dev, n_images, workspace) -> None:
+    """Device placement and sizes that the C ABI cannot see (it takes bare
+    pointers): arenas of one type and size, a table of at least n_images
+    descriptors, all contiguous device tensors."""
+    for name, t in (("in_arena", in_arena), ("out_arena", out_arena), ("table", table_dev),
+                    ("workspace", workspace)):
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous device tensor")
+    if out_arena.dtype != in_arena.dtype or out_arena.numel() != in_arena.numel():
+        raise ValueError("input and output arenas must match in type and size")
+    if table_dev.numel() * table_dev.element_size() < int(n_images) * DESC_DTYPE.itemsize:
+        raise ValueError(f"the table holds fewer than {n_images} descriptors")
+
+
 def edge_batch(in_arena: torch.Tensor, out_arena: torch.Tensor, table_dev: torch.Tensor,
                n_images: int, workspace: torch.Tensor, *, border: str = "white",
                mode: str = "masks", clause2_only: bool = False, invert: bool = False, cfg=None,
@@ -128,8 +142,7 @@ def edge_batch(in_arena: torch.Tensor, out_arena: torch.Tensor, table_dev: torch
     workspace (see plan_batch)."""
     from . import stream_handle
     wb = _word_bits(in_arena)
-    if out_arena.dtype != in_arena.dtype or out_arena.numel() != in_arena.numel():
-        raise ValueError("input and output arenas must match in type and size")
+    _check_batch_tensors(in_arena, out_arena, table_dev, n_images, workspace)
     cfg = _resolve(cfg, n_images, in_arena.numel(), wb, mode)
     check(_lib.edge_batch(in_arena.data_ptr(), out_arena.data_ptr(), in_arena.numel(),
                           table_dev.data_ptr(), n_images, wb, _BORDERS[border], _MODES[mode],
@@ -150,6 +163,7 @@ class BatchGraph:
                  border="white", mode="masks", clause2_only=False, invert=False, cfg=None,
                  planned=False):
         wb = _word_bits(in_arena)
+        _check_batch_tensors(in_arena, out_arena, table_dev, n_images, workspace)
         cfg = _resolve(cfg, n_images, in_arena.numel(), wb, mode)
         self._keep = (in_arena, out_arena, table_dev, workspace)
         h = ctypes.c_void_p()

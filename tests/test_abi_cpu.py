@@ -197,3 +197,21 @@ def test_planned_flag_and_host_plan_validation():
     buf = np.zeros(lib.edge_batch_workspace_bytes(1) // 8, np.int64)
     assert lib.edge_batch_plan(A, B, 100, bad.ctypes.data, 1, 32, None, buf.ctypes.data,
                                buf.nbytes, ctypes.byref(used)) == INVALID
+
+
+def test_binding_rejects_host_tensors():
+    """The C ABI takes bare pointers and cannot tell host memory from
+    device memory; the Python binding refuses host tensors before the call."""
+    import torch
+    import paper_1401_5245_amd as em
+    a, b = torch.zeros(64, dtype=torch.int64), torch.zeros(64, dtype=torch.int64)
+    with pytest.raises(ValueError):
+        em.copy_bytes(a, b, 16)
+    with pytest.raises(ValueError):
+        em.edge_masks(a.view(4, 16), b.view(4, 16), 4, 64)
+    with pytest.raises(ValueError):
+        em.peel(a.view(4, 16), b.view(4, 16), 4, 64, 2)
+    ws = torch.zeros(em.batch_workspace_bytes(1), dtype=torch.uint8)
+    table = torch.zeros(3, dtype=torch.int64)
+    with pytest.raises(ValueError):
+        em.edge_batch(a, b, table, 1, ws)
