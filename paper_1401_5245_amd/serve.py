@@ -54,6 +54,8 @@ def _copy_async(dst: torch.Tensor, dst_off: int, src: torch.Tensor, src_off: int
     if not (0 <= src_off and src_off + n <= src.numel() and 0 <= dst_off
             and dst_off + n <= dst.numel()):
         raise ValueError("copy outside its tensors")
+    if dst.element_size() != src.element_size():
+        raise ValueError("source and destination differ in element size")
     es = src.element_size()
     rc = _hip().hipMemcpyAsync(dst.data_ptr() + dst_off * es, src.data_ptr() + src_off * es,
                                n * es, _HIP_MEMCPY_DEFAULT, stream.cuda_stream)
