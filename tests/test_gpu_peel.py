@@ -163,3 +163,22 @@ def test_peel_deep_levels(k):
                         cache_policy=0)
                     got = run_peel(img, wb, k, border=border, edge_out=edge_out, cfg=cfg)
                     assert_same(got, want, f"{H}x{W} k={k} {border} edge_out={edge_out} rows={rows}")
+
+
+@pytest.mark.parametrize("k,edge_out", [(0, False), (1, False), (0, True)])
+@pytest.mark.parametrize("cfg", [None,
+                                 dict(vec_words=4, rows_per_tile=2, waves_per_block=4,
+                                      blocks_per_cu=1, cache_policy=2),
+                                 dict(vec_words=2, rows_per_tile=7, waves_per_block=1,
+                                      blocks_per_cu=1, cache_policy=1)])
+def test_single_level_on_strip_loop(k, edge_out, cfg):
+    """One level or none runs the edge kernels' strip loop (any vector
+    width, narrow rows included); odd strides force narrower loads."""
+    for (H, W, wb, extra) in ((70, 8193, 32, 1), (33, 4100, 64, 0), (41, 900, 32, 3),
+                              (9, 20000, 64, 1)):
+        img = sparse_white(H, W, seed=H + W + k, p=0.05)
+        for border in ("white", "black"):
+            got = run_peel(img, wb, k, border=border, edge_out=edge_out, cfg=cfg,
+                           stride_extra=extra)
+            assert_same(got, oracle.peel(img, k, border=border, edge_out=edge_out),
+                        f"{H}x{W} B={wb} k={k} edge_out={edge_out} {border} cfg={cfg}")
