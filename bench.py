@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--headline-only", action="store_true",
                    help="time only the headline workload (no other configs, no CPU baseline)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--serve-only", action="store_true",
                    help="run only the serving sweep (prints its JSON)")
     p.add_argument("--batch-only", action="store_true",
@@ -841,7 +841,7 @@ def cpu_baseline(img, seconds):
         oracle.edge(img)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= seconds or reps >= 100:
+        if el >= seconds or reps >= 400:
             break
     gpx = img.size * reps / el / 1e9
     return {"value": round(gpx, 4), "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
