@@ -392,6 +392,19 @@ def batched_crops(torch, em, tm, steps):
 
     per_image(0)
     ms_plain = tm.per_call_ms(per_image, max(3, min(20, steps // 50)))
+    # Device rates with the host out of the loop: one graph holding 20
+    # launches of the batch, and one graph holding the 4096 per-crop
+    # launches (each call above is one host submission, which a graph of
+    # a single node does not make cheaper).
+    from paper_1401_5245_amd.tune import _graph_time_us
+
+    def per_image_here():
+        st = int(torch.cuda.current_stream().cuda_stream)
+        for (pi, po, h, w, s) in calls:
+            lib.edge_masks(pi, po, h, w, s, 32, 0, st)
+
+    us_graph20 = _graph_time_us(lambda: b.run(), 20, max(5, steps // 200))
+    us_plain_graph = _graph_time_us(per_image_here, 1, 3)
     return {"workload": "batched, 4096 glyph crops H,W log-uniform [24,256] (seed 3), uint32, "
                         "%.1f Mpx" % (px / 1e6),
             "gpx_s_graph": round(px / (ms_graph * 1e-3) / 1e9, 1),
@@ -399,6 +412,10 @@ def batched_crops(torch, em, tm, steps):
             "gpx_s_per_image_launches": round(px / (ms_plain * 1e-3) / 1e9, 2),
             "speedup_vs_per_image": round(ms_plain / ms_graph, 1),
             "us_graph": round(ms_graph * 1e3, 2),
+            "us_per_launch_graph_of_20": round(us_graph20, 2),
+            "gpx_s_graph_of_20": round(px / (us_graph20 * 1e-6) / 1e9, 1),
+            "gpx_s_per_image_launches_in_one_graph": round(px / (us_plain_graph * 1e-6) / 1e9, 2),
+            "speedup_graph_of_20_vs_per_image_graph": round(us_plain_graph / us_graph20, 1),
             "cfg": tune.lookup_batch(b.n, b.inp.numel(), 32) or em.default_cfg(0, 0, 32, batch=True),
             "bit_exact_first_256": exact}
 
