@@ -81,3 +81,69 @@ def test_tallest_image():
         for name, out in outs.items():
             got = unpack_rows(out[y:y + 1].cpu().numpy().view(np.uint64), W)
             assert_same(got, oracle_of(name, win)[y - lo:y - lo + 1], f"{name} row {y}")
+
+
+def test_widest_rows_planes_and_grey():
+    """Direction planes and grey input (threshold fused into the edge pass)
+    on 3 rows of 2^31 - 1 pixels: 3 GiB of planes, 6 GiB of grey bytes."""
+    import paper_1401_5245_amd as em
+    torch.cuda.empty_cache()
+    H, W = 3, 2**31 - 1
+    wd = (W + 63) // 64
+    log(f"widest rows, planes and grey: {H} x {W}")
+    inp = random_words((H, wd))
+    planes = torch.empty((4, H, wd), dtype=torch.int64, device="cuda")
+    em.edge_directions(inp, planes, H, W)
+    gs = 2**31                                       # 16-byte aligned grey rows
+    grey = torch.randint(0, 256, (H, gs), dtype=torch.uint8, device="cuda")
+    gout = torch.empty((H, wd), dtype=torch.int64, device="cuda")
+    em.threshold_edges(grey, gout, H, W, 128, grey_stride=gs)
+    torch.cuda.synchronize()
+    for a, b in ((0, 2), (wd // 2 - 1, wd // 2 + 1), (wd - 2, wd)):
+        lo, hi = max(0, a - 1), min(wd, b + 1)       # one word of margin where the row goes on
+        width = min(W, 64 * hi) - 64 * lo
+        x0, x1 = 64 * (a - lo), min(W, 64 * b) - 64 * lo
+        win = unpack_rows(inp[:, lo:hi].cpu().numpy().view(np.uint64), width)
+        want = oracle.fundamental_edges(win)
+        for p in range(4):
+            got = unpack_rows(planes[p, :, lo:hi].cpu().numpy().view(np.uint64), width)
+            assert_same(got[:, x0:x1], want[p][:, x0:x1], f"plane {p} words {a}..{b}")
+        gwin = grey[:, 64 * lo:64 * lo + width].cpu().numpy()
+        want = oracle.edge(oracle.threshold(gwin, 128))
+        got = unpack_rows(gout[:, lo:hi].cpu().numpy().view(np.uint64), width)
+        assert_same(got[:, x0:x1], want[:, x0:x1], f"grey words {a}..{b}")
+    del inp, planes, grey, gout
+    torch.cuda.empty_cache()
+
+
+def test_tallest_image_planes_and_grey():
+    """Direction planes and grey input on EDGE_MAX_HEIGHT rows of 64 pixels:
+    32 GiB of planes, 64 GiB of grey bytes."""
+    import paper_1401_5245_amd as em
+    torch.cuda.empty_cache()
+    H, W = _abi.EDGE_MAX_HEIGHT, 64
+    log(f"tallest image, planes and grey: {H} x {W}")
+    inp = random_words((H, 1))
+    planes = torch.empty((4, H, 1), dtype=torch.int64, device="cuda")
+    em.edge_directions(inp, planes, H, W)
+    torch.cuda.synchronize()
+    rows = (0, 1, 2, H // 2, H - 3, H - 2, H - 1)
+    for y in rows:
+        lo, hi = max(0, y - 2), min(H, y + 3)
+        want = oracle.fundamental_edges(unpack_rows(inp[lo:hi].cpu().numpy().view(np.uint64), W))
+        for p in range(4):
+            got = unpack_rows(planes[p, y:y + 1].cpu().numpy().view(np.uint64), W)
+            assert_same(got, want[p][y - lo:y - lo + 1], f"plane {p} row {y}")
+    del inp, planes
+    torch.cuda.empty_cache()
+    grey = torch.randint(0, 256, (H, W), dtype=torch.uint8, device="cuda")
+    gout = torch.empty((H, 1), dtype=torch.int64, device="cuda")
+    em.threshold_edges(grey, gout, H, W, 128)
+    torch.cuda.synchronize()
+    for y in rows:
+        lo, hi = max(0, y - 2), min(H, y + 3)
+        want = oracle.edge(oracle.threshold(grey[lo:hi].cpu().numpy(), 128))
+        got = unpack_rows(gout[y:y + 1].cpu().numpy().view(np.uint64), W)
+        assert_same(got, want[y - lo:y - lo + 1], f"grey row {y}")
+    del grey, gout
+    torch.cuda.empty_cache()
