@@ -147,3 +147,64 @@ def test_tallest_image_planes_and_grey():
         assert_same(got, want[y - lo:y - lo + 1], f"grey row {y}")
     del grey, gout
     torch.cuda.empty_cache()
+
+
+def test_batch_with_extreme_images():
+    """One persistent batch launch over a table that holds the tallest image
+    (EDGE_MAX_HEIGHT rows of 64 pixels) and the widest one (3 rows of
+    2^31 - 1 pixels) between small crops: 64-bit arena offsets and millions
+    of work units per image, with the host and the device planner."""
+    import paper_1401_5245_amd as em
+    from paper_1401_5245_amd import batch as B
+    torch.cuda.empty_cache()
+    tall, wide = _abi.EDGE_MAX_HEIGHT, 2**31 - 1
+    shapes = [(5, 70), (tall, 64), (3, 33), (3, wide), (40, 257)]
+    table = np.zeros(len(shapes), dtype=B.DESC_DTYPE)
+    off = 0
+    for i, (h, w) in enumerate(shapes):
+        s = -(-w // 64)
+        off = -(-off // 2) * 2                       # 16-byte aligned images
+        table[i] = (off, h, w, s)
+        off += h * s
+    total = -(-off // 2) * 2
+    log(f"batch with extreme images: {total} words")
+    B.check_table(table, total, 64)
+    inp = random_words((total,))
+    out = torch.zeros_like(inp)
+    table_dev = B.table_to_device(table)
+    ws = torch.zeros(-(-B.batch_workspace_bytes(len(table)) // 8), dtype=torch.int64,
+                     device="cuda")
+
+    def image(t, i):
+        o, h, s = int(table[i]["offset_words"]), int(table[i]["height"]), int(table[i]["stride_words"])
+        return t[o:o + h * s].view(h, s)
+
+    for plan in ("host", "device"):
+        out.zero_()
+        if plan == "host":
+            words, used = B.plan_batch(inp, out, table)
+            ws[:-(-used // 8)].copy_(torch.from_numpy(words[:-(-used // 8)]))
+        em.edge_batch(inp, out, table_dev, len(table), ws, planned=plan == "host")
+        torch.cuda.synchronize()
+        for i in (0, 2, 4):
+            h, w = shapes[i]
+            want = oracle.edge(unpack_rows(image(inp, i).cpu().numpy().view(np.uint64), w))
+            got = unpack_rows(image(out, i).cpu().numpy().view(np.uint64), w)
+            assert_same(got, want, f"{plan} plan: crop {i}")
+        ti, to = image(inp, 1), image(out, 1)
+        for y in (0, 1, tall // 2, tall - 2, tall - 1):
+            lo, hi = max(0, y - 1), min(tall, y + 2)
+            want = oracle.edge(unpack_rows(ti[lo:hi].cpu().numpy().view(np.uint64), 64))
+            got = unpack_rows(to[y:y + 1].cpu().numpy().view(np.uint64), 64)
+            assert_same(got, want[y - lo:y - lo + 1], f"{plan} plan: tall image row {y}")
+        wi, wo = image(inp, 3), image(out, 3)
+        wd = wi.shape[1]
+        for a, b in ((0, 2), (wd // 2 - 1, wd // 2 + 1), (wd - 2, wd)):
+            lo, hi = max(0, a - 1), min(wd, b + 1)
+            width = min(wide, 64 * hi) - 64 * lo
+            x0, x1 = 64 * (a - lo), min(wide, 64 * b) - 64 * lo
+            want = oracle.edge(unpack_rows(wi[:, lo:hi].cpu().numpy().view(np.uint64), width))
+            got = unpack_rows(wo[:, lo:hi].cpu().numpy().view(np.uint64), width)
+            assert_same(got[:, x0:x1], want[:, x0:x1], f"{plan} plan: wide image words {a}..{b}")
+    del inp, out
+    torch.cuda.empty_cache()
