@@ -1,8 +1,8 @@
 /* The library driven from plain C: device memory from the HIP runtime's C
  * API, no Python and no PyTorch. Each case runs an entry point on a seeded
- * random image and compares every pixel with the oracle's C functions (this
- * program is test infrastructure, so it may call both). Prints one line per
- * case; exits 0 when every case matches. */
+ * random image (or a batch of them) and compares every pixel with the
+ * oracle's C functions (this program is test infrastructure, so it may call
+ * both). Prints one line per case; exits 0 when every case matches. */
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -101,6 +101,98 @@ static int run_case(int64_t H, int64_t W, int border, int kind, uint64_t seed) {
     return ok;
 }
 
+/* One batch of uneven images (32-bit words) in one arena, run with the
+ * device planner and again with the host plan (EDGE_FLAG_PLANNED); every
+ * image compared with the oracle. Returns 1 when both runs match. */
+static int run_batch_case(int border, uint64_t seed) {
+    enum { N = 24 };
+    edge_image_desc tab[N];
+    int64_t off = 0, i, y, x;
+    int ok = 1, pass;
+    rng_state = seed;
+    for (i = 0; i < N; ++i) {
+        const int64_t h = 1 + (int64_t)(next_u64() % 150), w = 1 + (int64_t)(next_u64() % 600);
+        const int64_t s = (w + 31) / 32 + (int64_t)(next_u64() % 3);
+        off = (off + 3) / 4 * 4; /* 16-byte aligned images */
+        tab[i].offset_words = off;
+        tab[i].height = (int32_t)h;
+        tab[i].width = (int32_t)w;
+        tab[i].stride_words = s;
+        off += h * s;
+    }
+    const int64_t words = (off + 3) / 4 * 4;
+    uint32_t* arena = malloc((size_t)words * 4);
+    uint32_t* back = malloc((size_t)words * 4);
+    const int64_t ws_bytes = edge_batch_workspace_bytes(N);
+    void* plan = malloc((size_t)ws_bytes);
+    void *din = NULL, *dout = NULL, *dtab = NULL, *dws = NULL;
+    int64_t used = 0;
+    for (i = 0; i < words; ++i) arena[i] = (uint32_t)(next_u64() & next_u64());
+    if (edge_batch_check(tab, N, words, 32) != EDGE_OK) {
+        printf("batch table rejected\n");
+        return 0;
+    }
+    HIP_OK(hipMalloc(&din, (size_t)words * 4));
+    HIP_OK(hipMalloc(&dout, (size_t)words * 4));
+    HIP_OK(hipMalloc(&dtab, sizeof(tab)));
+    HIP_OK(hipMalloc(&dws, (size_t)ws_bytes));
+    HIP_OK(hipMemcpy(din, arena, (size_t)words * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(dtab, tab, sizeof(tab), hipMemcpyHostToDevice));
+    for (pass = 0; pass < 2 && ok; ++pass) {
+        int rc;
+        uint32_t flags = 0u;
+        HIP_OK(hipMemset(dout, 0, (size_t)words * 4));
+        if (pass == 1) {
+            rc = edge_batch_plan(din, dout, words, tab, N, 32, NULL, plan, ws_bytes, &used);
+            if (rc != EDGE_OK) {
+                printf("edge_batch_plan returned %d (%s)\n", rc, edge_status_string(rc));
+                ok = 0;
+                break;
+            }
+            HIP_OK(hipMemcpy(dws, plan, (size_t)used, hipMemcpyHostToDevice));
+            flags = EDGE_FLAG_PLANNED;
+        }
+        rc = edge_batch(din, dout, words, (const edge_image_desc*)dtab, N, 32, border,
+                        EDGE_MODE_MASKS, flags, NULL, dws, ws_bytes, NULL);
+        if (rc != EDGE_OK) {
+            printf("edge_batch returned %d (%s)\n", rc, edge_status_string(rc));
+            ok = 0;
+            break;
+        }
+        HIP_OK(hipDeviceSynchronize());
+        HIP_OK(hipMemcpy(back, dout, (size_t)words * 4, hipMemcpyDeviceToHost));
+        for (i = 0; i < N && ok; ++i) {
+            const int64_t h = tab[i].height, w = tab[i].width, s = tab[i].stride_words;
+            const uint32_t* in = arena + tab[i].offset_words;
+            const uint32_t* got = back + tab[i].offset_words;
+            uint8_t* img = malloc((size_t)(h * w));
+            uint8_t* want = malloc((size_t)(h * w));
+            for (y = 0; y < h; ++y)
+                for (x = 0; x < w; ++x) img[y * w + x] = (uint8_t)((in[y * s + x / 32] >> (x % 32)) & 1);
+            oracle_edge_image(img, want, h, w, border == EDGE_BORDER_WHITE, 1, 0);
+            for (y = 0; y < h && ok; ++y)
+                for (x = 0; x < w; ++x)
+                    if ((uint8_t)((got[y * s + x / 32] >> (x % 32)) & 1) != want[y * w + x]) {
+                        printf("batch pass %d image %lld pixel (%lld, %lld) differs\n", pass,
+                               (long long)i, (long long)y, (long long)x);
+                        ok = 0;
+                        break;
+                    }
+            free(img);
+            free(want);
+        }
+    }
+    HIP_OK(hipFree(din));
+    HIP_OK(hipFree(dout));
+    HIP_OK(hipFree(dtab));
+    HIP_OK(hipFree(dws));
+    free(arena);
+    free(back);
+    free(plan);
+    printf("%s batch of %d images border %d\n", ok ? "match" : "MISMATCH", N, border);
+    return ok;
+}
+
 int main(void) {
     static const int64_t shapes[][2] = {{1, 1}, {3, 33}, {5, 64}, {70, 1000}, {257, 2049},
                                         {33, 8193}};
@@ -116,6 +208,10 @@ int main(void) {
                                 1000u * (uint64_t)s + 10u * (uint64_t)border + (uint64_t)kind);
                 ++cases;
             }
+    for (int border = 0; border < 2; ++border) {
+        all &= run_batch_case(border, 77u + (uint64_t)border);
+        ++cases;
+    }
     printf("%s: %d cases\n", all ? "all match" : "FAILED", cases);
     return all ? 0 : 1;
 }
