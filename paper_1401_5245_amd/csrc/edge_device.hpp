@@ -595,6 +595,148 @@ __device__ __forceinline__ void peel_unit(const Geom& g, int64_t chunk, int y0, 
         if (t + u <= tlast) step(all, t + u, q[u]);
 }
 
+// Peeling with VW consecutive words per lane (one 64- or 128-bit load and
+// store per row, VW = 2 or 4) for up to kPeelVecLevels levels: the
+// wavefront covers 64 * VW words of each row and has no halo lanes. The word
+// just left of its span (held by lane 0) and the word just right of it
+// (lane 63) sit in one more register per level and form their levels too,
+// with black shifted in from beyond them; the error that brings starts at
+// their far bits and moves one pixel per level, so with L <= 31 the bit next
+// to the span stays exact (the argument of the halo lanes of peel_unit).
+// Per level and row: the words' funnel shifts and ORs as in peel_unit, the
+// DPP carries once per lane, the halo word's own level. Warm-up as in
+// peel_unit. WHOLE: the span lies inside the row (vector loads and stores).
+// Used up to three levels, where its lane work per word is lowest against
+// the memory work and every instantiation is checked against the oracle.
+constexpr int kPeelVecLevels = 3;
+
+template <int L, bool EDGEOUT, int VW, bool WHOLE, class Pol>
+__device__ __forceinline__ void peel_vec_unit(const Geom& g, int j0, int y0, int y1,
+                                              uint32_t bw) {
+    static_assert(L >= 1 && L <= 31, "the halo words carry 32 pixels");
+    constexpr int P = kPeelGroup;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int jl = j0 + lane * VW;
+    uint32_t vm[VW], om[VW];
+    int jw[VW];
+    bool inrow[VW];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+        vm[k] = valid_bits(jl + k, g.width);
+        om[k] = bw & ~vm[k];
+        inrow[k] = jl + k < g.wd;
+        jw[k] = inrow[k] ? jl + k : g.wd - 1;
+    }
+    const bool first = lane == 0;
+    const int jh = first ? j0 - 1 : j0 + kWave * VW;     // lanes 0 and 63; the rest unused
+    const bool hin = jh >= 0 && jh < g.wd;
+    const uint32_t vmh = hin ? valid_bits(jh, g.width) : 0u;
+    const uint32_t omh = bw & ~vmh;
+    const int jhl = hin ? jh : (jh < 0 ? 0 : g.wd - 1);
+
+    struct Raw { uint32_t w[VW]; uint32_t h; };
+    auto load = [&](int y) -> Raw {
+        const int yc = y < 0 ? 0 : (y >= g.height ? g.height - 1 : y);
+        const uint32_t* rp = g.in + (int64_t)yc * g.stride;
+        Raw r;
+        if constexpr (WHOLE) {
+            load_words<VW, Pol::nt_load>(rp + jl, r.w);
+        } else {
+#pragma unroll
+            for (int k = 0; k < VW; ++k) r.w[k] = rp[jw[k]];
+        }
+        r.h = rp[jhl];
+        return r;
+    };
+
+    uint32_t A[L][VW], B[L][VW], Ah[L], Bh[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+#pragma unroll
+        for (int k = 0; k < VW; ++k) { A[i][k] = bw; B[i][k] = bw; }
+        Ah[i] = bw;
+        Bh[i] = bw;
+    }
+
+    // one step forming levels 1..ACT (the levels above only pass rows along)
+    auto step = [&](auto act_tag, int t, const Raw& raw) {
+        constexpr int ACT = decltype(act_tag)::value;
+        const bool inside = (unsigned)t < (unsigned)g.height;
+        uint32_t n[VW];
+#pragma unroll
+        for (int k = 0; k < VW; ++k) n[k] = inside ? ((raw.w[k] & vm[k]) | om[k]) : bw;
+        uint32_t nh = inside ? ((raw.h & vmh) | omh) : bw;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            uint32_t c[VW], v[VW];
+#pragma unroll
+            for (int k = 0; k < VW; ++k) { c[k] = B[i][k]; v[k] = c[k]; }
+            const uint32_t ch = Bh[i];
+            uint32_t vh = ch;
+            if (i < ACT) {
+                // lane 0 takes its left halo word, lane 63 its right one
+                const uint32_t wi = from_lower_lane(c[VW - 1], ch);
+                const uint32_t ei = from_upper_lane(c[0], ch);
+#pragma unroll
+                for (int k = 0; k < VW; ++k) {
+                    const uint32_t w = west_of(c[k], k > 0 ? c[k - 1] : wi);
+                    const uint32_t e = east_of(c[k], k + 1 < VW ? c[k + 1] : ei);
+                    v[k] = (c[k] | w | e) | (A[i][k] | n[k]);
+                }
+                const uint32_t hx = first ? 0u : c[VW - 1], hy = first ? c[0] : 0u;
+                vh = (ch | west_of(ch, hx) | east_of(ch, hy)) | (Ah[i] | nh);
+            }
+#pragma unroll
+            for (int k = 0; k < VW; ++k) {
+                A[i][k] = c[k];
+                B[i][k] = n[k];
+                n[k] = v[k];
+            }
+            Ah[i] = ch;
+            Bh[i] = nh;
+            nh = vh;
+        }
+        const int y = t - L;                  // n = L_L(y); A[L-1] = L_{L-1}(y)
+        if (y >= y0) {
+            uint32_t res[VW];
+#pragma unroll
+            for (int k = 0; k < VW; ++k) res[k] = (EDGEOUT ? (n[k] & ~A[L - 1][k]) : n[k]) & vm[k];
+            uint32_t* op = g.out + (int64_t)y * g.stride;
+            if constexpr (WHOLE) {
+                store_words<VW, Pol::nt_store>(op + jl, res);
+            } else {
+#pragma unroll
+                for (int k = 0; k < VW; ++k)
+                    if (inrow[k]) op[jl + k] = res[k];
+            }
+        }
+    };
+
+    const int t0 = y0 - L, tlast = y1 - 1 + L;
+    Raw q[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) q[u] = load(min(t0 + u, tlast));
+    auto group = [&](auto act_tag, int t) {
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            const Raw w = q[u];
+            q[u] = load(min(t + u + P, tlast));
+            step(act_tag, t + u, w);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    constexpr auto all = std::integral_constant<int, L>{};
+    int t = t0;
+    if constexpr (L > kPeelPhase) {
+        for (; t - t0 < 2 * L && t + P <= tlast + 1; t += P)
+            peel_phase<L>(peel_formed(t - t0, P, 0, L), [&](auto a) { group(a, t); });
+    }
+    for (; t + P <= tlast + 1; t += P) group(all, t);
+#pragma unroll
+    for (int u = 0; u + 1 < P; ++u)
+        if (t + u <= tlast) step(all, t + u, q[u]);
+}
+
 // Peeling with the levels of one strip split over two wavefronts of a
 // workgroup (twice the wavefronts for the same halo rows, half the
 // registers each). Wavefront 0 loads the rows and forms levels 1..LA for a

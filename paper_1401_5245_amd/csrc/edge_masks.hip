@@ -70,6 +70,26 @@ __global__ void __launch_bounds__(512) k_peel(Geom g, int64_t chunks, int rows, 
     peel_unit<L, EDGEOUT, Pol>(g, chunk, (int)y0, (int)y1, bw);
 }
 
+// Iterated peeling with VW words per lane: strips of `rows` rows x 64*VW
+// words, one wavefront per strip, L levels.
+template <int L, bool EDGEOUT, int VW>
+__global__ void __launch_bounds__(512) k_peel_vec(Geom g, int64_t chunks, int rows,
+                                                  int64_t nunits, uint32_t bw) {
+    const int wpb = blockDim.x / kWave;
+    const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
+                         wave_uniform(threadIdx.x / kWave);
+    if (unit >= nunits) return;
+    const int64_t strip = unit / chunks;
+    const int64_t chunk = unit - strip * chunks;
+    const int64_t y0 = strip * rows;
+    const int64_t y1 = y0 + rows < g.height ? y0 + rows : g.height;
+    const int j0 = (int)(chunk * kWave * VW);
+    if (j0 + kWave * VW <= g.wd)
+        peel_vec_unit<L, EDGEOUT, VW, true, CachedStrip>(g, j0, (int)y0, (int)y1, bw);
+    else
+        peel_vec_unit<L, EDGEOUT, VW, false, CachedStrip>(g, j0, (int)y0, (int)y1, bw);
+}
+
 // Iterated peeling with a strip's levels split over the two wavefronts of
 // a workgroup (one strip per workgroup, so both leave together).
 template <int LA, int LB, bool EDGEOUT>
@@ -825,6 +845,18 @@ int launch_peel_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, hip
     return launch_status();
 }
 
+template <int L, bool EDGEOUT, int VW>
+int launch_peel_vec_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, hipStream_t s) {
+    const int64_t chunks = ceil_div(g.wd, (int64_t)kWave * VW);
+    const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
+    const int64_t blocks = ceil_div(nunits, c.waves_per_block);
+    if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL((k_peel_vec<L, EDGEOUT, VW>), dim3((uint32_t)blocks),
+                       dim3(c.waves_per_block * kWave), 0, s, g, chunks, c.rows_per_tile, nunits,
+                       bw);
+    return launch_status();
+}
+
 // From this many levels a strip's levels are split over two wavefronts.
 constexpr int kPeelSplitLevels = 16;
 
@@ -842,18 +874,26 @@ int launch_peel_split_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t b
 
 // One instantiation per level count 2..31 (levels are a template constant
 // so that every level's rows stay in registers).
+// vw: words per lane that the image's alignment allows (2 or 4 select the
+// vector-width unit up to kPeelVecLevels levels).
 template <int L, bool EDGEOUT>
-int launch_peel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int levels, hipStream_t s) {
+int launch_peel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int levels, int vw,
+                hipStream_t s) {
     if constexpr (L > 31) {
         return EDGE_ERR_INVALID;
     } else {
         if (levels == L) {
-            if constexpr (L >= kPeelSplitLevels)
+            if constexpr (L >= kPeelSplitLevels) {
                 return launch_peel_split_kernel<L, EDGEOUT>(g, c, bw, s);
-            else
+            } else if constexpr (L <= kPeelVecLevels) {
+                if (vw == 4) return launch_peel_vec_kernel<L, EDGEOUT, 4>(g, c, bw, s);
+                if (vw == 2) return launch_peel_vec_kernel<L, EDGEOUT, 2>(g, c, bw, s);
                 return launch_peel_kernel<L, EDGEOUT>(g, c, bw, s);
+            } else {
+                return launch_peel_kernel<L, EDGEOUT>(g, c, bw, s);
+            }
         }
-        return launch_peel<L + 1, EDGEOUT>(g, c, bw, levels, s);
+        return launch_peel<L + 1, EDGEOUT>(g, c, bw, levels, vw, s);
     }
 }
 
@@ -867,7 +907,7 @@ int launch_peel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int levels
 // neighbouring strips share.
 edge_launch_cfg default_peel(int64_t height, int64_t wd32, int levels) {
     edge_launch_cfg c;
-    c.vec_words = 1;
+    c.vec_words = levels <= kPeelVecLevels ? 4 : 1;
     c.blocks_per_cu = 1;
     c.cache_policy = EDGE_CACHE_NORMAL;
     c.waves_per_block = 4;
@@ -1087,8 +1127,10 @@ int edge_peel(const void* in, void* out, int64_t height, int64_t width, int64_t 
         return launch_single<kModePeel>(g, vw, c, bw, 0, s);
     }
     const edge_launch_cfg c = cfg ? *cfg : default_peel(height, g.wd, levels);
-    if (edge_out) return launch_peel<2, true>(g, c, bw, levels, s);
-    return launch_peel<2, false>(g, c, bw, levels, s);
+    const int vmax = std::min(c.vec_words, std::min(alignment_words(pin), alignment_words(pout)));
+    const int vw = pick_vw(g.wd, vmax, 0, g.stride);
+    if (edge_out) return launch_peel<2, true>(g, c, bw, levels, vw, s);
+    return launch_peel<2, false>(g, c, bw, levels, vw, s);
 }
 
 int edge_masks_staged(const void* in, void* out, void* scratch, int64_t scratch_bytes,

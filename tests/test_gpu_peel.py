@@ -182,3 +182,23 @@ def test_single_level_on_strip_loop(k, edge_out, cfg):
                            stride_extra=extra)
             assert_same(got, oracle.peel(img, k, border=border, edge_out=edge_out),
                         f"{H}x{W} B={wb} k={k} edge_out={edge_out} {border} cfg={cfg}")
+
+
+@pytest.mark.parametrize("vec", [1, 2, 4])
+@pytest.mark.parametrize("edge_out", [False, True])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7])
+def test_peel_vector_widths(vec, k, edge_out):
+    """Up to seven levels with one, two or four words per lane (strides that
+    do not divide by the width fall back to narrower loads), sparse content
+    so that every level still changes the image."""
+    for (H, W, wb, extra) in ((70, 8193, 32, 0), (33, 4100, 64, 0), (41, 900, 32, 3),
+                              (9, 20000, 64, 1), (130, 2100, 32, 4)):
+        img = sparse_white(H, W, seed=H + W + k, p=0.003)
+        for border in ("white", "black"):
+            want = oracle.peel(img, k, border=border, edge_out=edge_out)
+            for rows in (3, 8):
+                cfg = dict(vec_words=vec, rows_per_tile=rows, waves_per_block=2, blocks_per_cu=1,
+                           cache_policy=0)
+                got = run_peel(img, wb, k, border=border, edge_out=edge_out, cfg=cfg,
+                               stride_extra=extra)
+                assert_same(got, want, f"{H}x{W} B={wb} k={k} {border} vec={vec} rows={rows}")
