@@ -206,10 +206,11 @@ int edge_masks_staged(const void* in, void* out, void* scratch, int64_t scratch_
  * 0 <= iterations <= EDGE_PEEL_MAX_ITERATIONS, all done in one pass over
  * the image. cfg: NULL, or a configuration. With two or more levels
  * (iterations, plus one with EDGE_FLAG_PEEL_EDGE) its rows_per_tile and
- * waves_per_block are used (loads always go through the caches; from 16
- * levels each strip takes one workgroup of two wavefronts); one level or
- * none runs the strip loop of edge_image_launch, which reads every field
- * as that call does. */
+ * waves_per_block are used, and with two or three levels also vec_words
+ * (words per lane, narrowed as the pointers and stride require); loads
+ * always go through the caches, and from 16 levels each strip takes one
+ * workgroup of two wavefronts. One level or none runs the strip loop of
+ * edge_image_launch, which reads every field as that call does. */
 int edge_peel(const void* in, void* out, int64_t height, int64_t width, int64_t stride_words,
               int word_bits, int border, int iterations, uint32_t flags,
               const edge_launch_cfg* cfg, void* hip_stream);
