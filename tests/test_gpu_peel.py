@@ -94,7 +94,7 @@ def oracle_rows(img, k, rows, border="white", edge_out=False):
     return np.stack(out)
 
 
-@pytest.mark.parametrize("k", [1, 8, 30])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 7, 8, 30])
 def test_peel_8192_sampled_rows(k):
     """The 8192^2 glyph page in uint64 words, in the built-in launch shape:
     sampled rows against the oracle on row windows."""
