@@ -202,3 +202,20 @@ def test_peel_vector_widths(vec, k, edge_out):
                 got = run_peel(img, wb, k, border=border, edge_out=edge_out, cfg=cfg,
                                stride_extra=extra)
                 assert_same(got, want, f"{H}x{W} B={wb} k={k} {border} vec={vec} rows={rows}")
+
+
+@pytest.mark.parametrize("edge_out", [False, True])
+def test_every_level_count(edge_out):
+    """Every peel count 0..30 with both outputs, so that every kernel
+    instantiation (one per level count and output, and the vector-width
+    ones) runs: on seeded images whose every level still changes, with the
+    built-in shape and with one word per lane."""
+    one = dict(vec_words=1, rows_per_tile=8, waves_per_block=4, blocks_per_cu=1, cache_policy=0)
+    for (H, W, n, wb) in ((200, 3000, 6, 32), (150, 1000, 3, 64)):
+        img = white_seeds(H, W, n, seed=H + W)
+        for border in ("black", "white"):
+            for k in range(0, 31):
+                want = oracle.peel(img, k, border=border, edge_out=edge_out)
+                for cfg in (None, one):
+                    got = run_peel(img, wb, k, border=border, edge_out=edge_out, cfg=cfg)
+                    assert_same(got, want, f"{H}x{W} k={k} {border} cfg={cfg}")
