@@ -250,9 +250,10 @@ def _main(argv=None):
     import numpy as np
     import paper_1401_5245_amd as em
     ap = argparse.ArgumentParser(description="tune libedgemask launch configurations")
-    ap.add_argument("--out", default=DEFAULT_CACHE)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--out", default=DEFAULT_CACHE,
+                    help="JSON table to write (default: the user cache, %(default)s)")
+    ap.add_argument("--seed", type=int, default=0, help="seed of the random test images")
+    ap.add_argument("--verbose", action="store_true", help="print every candidate's time")
     ap.add_argument("--squares", default="",
                     help="comma-separated sides of square uint64 plain-method images to tune "
                          "instead of the default workloads (no batch)")
