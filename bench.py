@@ -34,16 +34,20 @@ def log(*a):
 
 
 def parse():
-    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    p.add_argument("--gpus", type=int, default=1)
+    p = argparse.ArgumentParser(description=" ".join(__doc__.split("\n\n")[0].split()))
+    p.add_argument("--gpus", type=int, default=1,
+                   help="GPUs to use; only 1 is supported (the benchmark runs on one GPU)")
     # about 22 ms of warm-up and of timed launches at 8192^2: long enough
     # for the clocks to settle and for one timed region to be stable
-    p.add_argument("--steps", type=int, default=4000)
-    p.add_argument("--warmup", type=int, default=4000)
+    p.add_argument("--steps", type=int, default=4000,
+                   help="timed launches of the headline workload")
+    p.add_argument("--warmup", type=int, default=4000,
+                   help="untimed launches before the timed region")
     p.add_argument("--headline-only", action="store_true",
                    help="time only the headline workload (no other configs, no CPU baseline)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--cpu-seconds", type=float, default=12.0,
+                   help="length of the one-thread oracle sample (the cpu_baseline field)")
     p.add_argument("--serve-only", action="store_true",
                    help="run only the serving sweep (prints its JSON)")
     p.add_argument("--batch-only", action="store_true",
