@@ -329,6 +329,65 @@ def plain_65536(torch, em, tm, steps):
             "roofline": roofline(nbytes, ms), "sampled_rows_bit_exact": ok}
 
 
+def next_rows_65536(torch, em, tm, steps=20):
+    """Direction planes and the fused threshold -> edges at 65536^2, where
+    every launch streams from HBM (2.7 GB and 4.8 GB per launch); sampled
+    rows against the oracle on windows."""
+    from synth import images, pack_rows, unpack_rows
+    import oracle
+    H = W = 65536
+    rows = (0, 1, 8191, 8192, 30000, 65534, 65535)
+
+    def window(tile, r):
+        lo, hi = max(0, r - 1), min(H, r + 2)
+        return lo, np.tile(np.stack([tile[y % 8192] for y in range(lo, hi)]), (1, 8))
+
+    res = {}
+    log("building 65536x65536 page (8x8 tiles of an 8192^2 glyph page, seed 22)")
+    tile_img = images.glyph_page(8192, 8192, seed=22)
+    words = np.tile(pack_rows(tile_img, 64), (8, 8))
+    inp = words_tensor(torch, words)
+    del words
+    out4 = torch.empty((4,) + tuple(inp.shape), dtype=inp.dtype, device="cuda")
+    em.edge_directions(inp, out4, H, W)
+    torch.cuda.synchronize()
+    ok = True
+    for r in rows:
+        lo, win = window(tile_img, r)
+        fe = oracle.fundamental_edges(win)
+        for p in range(4):
+            got = unpack_rows(out4[p, r:r + 1].cpu().numpy().view(np.uint64), W)[0]
+            ok &= bool(np.array_equal(got, fe[p][r - lo]))
+    ms = tm.per_call_ms(lambda i: em.edge_directions(inp, out4, H, W), steps)
+    nbytes = 5 * H * (W // 8)
+    res["directions"] = {"workload": "65536x65536 tiled glyph page (seed 22), uint64: four "
+                                     "fundamental-edge planes", "ms": round(ms, 4),
+                         "roofline": roofline(nbytes, ms), "sampled_rows_bit_exact": ok}
+    del inp, out4
+    torch.cuda.empty_cache()
+    log("building 65536x65536 grey image (8x8 tiles of the 8192^2 grey image, seed 7)")
+    grey_tile = images.grey_image(8192, 8192, seed=7)
+    gt = torch.from_numpy(grey_tile).cuda().repeat(8, 8)       # 4 GiB of grey bytes
+    out = torch.empty((H, W // 64), dtype=torch.int64, device="cuda")
+    em.threshold_edges(gt, out, H, W, 128)
+    torch.cuda.synchronize()
+    binary_tile = oracle.threshold(grey_tile, 128)
+    ok = True
+    for r in rows:
+        lo, win = window(binary_tile, r)
+        got = unpack_rows(out[r:r + 1].cpu().numpy().view(np.uint64), W)[0]
+        ok &= bool(np.array_equal(got, oracle.edge(win)[r - lo]))
+    ms = tm.per_call_ms(lambda i: em.threshold_edges(gt, out, H, W, 128), steps)
+    nbytes = H * W + H * (W // 8)
+    res["threshold_edges"] = {"workload": "65536x65536 tiled grey image (seed 7), threshold 128, "
+                                          "uint64 out", "ms": round(ms, 4),
+                              "gpx_s": round(H * W / (ms * 1e-3) / 1e9, 1),
+                              "roofline": roofline(nbytes, ms), "sampled_rows_bit_exact": ok}
+    del gt, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def full_16384(torch, em, tm, steps):
     from synth import images, pack_rows, unpack_rows
     import oracle
@@ -876,6 +935,7 @@ SECTIONS = {
     "full_16384": lambda torch, em, tm, a: full_16384(torch, em, tm, 50),
     "batched_4096": lambda torch, em, tm, a: batched_crops(torch, em, tm, a.steps),
     "next_rows": lambda torch, em, tm, a: next_rows(torch, em, tm, a.steps),
+    "next_rows_65536": lambda torch, em, tm, a: next_rows_65536(torch, em, tm),
     "size_sweep": lambda torch, em, tm, a: size_sweep(torch, em, tm),
     "content": lambda torch, em, tm, a: content_independence(torch, em, tm),
     "peel": lambda torch, em, tm, a: peel_section(torch, em, tm),
