@@ -260,15 +260,19 @@ def copy_ceiling(torch, em, tm, nbytes, nb, steps):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def launch_floor_ms(torch, em, tm, nl=40, reps=5):
+def launch_floor_ms(torch, em, tm, nl=40, reps=10, trials=7, warm=50):
     """Per-launch time of a near-empty kernel (the library's copy of 16
     bytes: one workgroup) replayed from a one-stream graph, as the headline
-    launches are: the fixed cost any launch pays."""
+    launches are: the fixed cost any launch pays. Warmed up first (it may
+    follow seconds of host-only work, after which the GPU idles at lower
+    clocks) and the median of several trials."""
     a = torch.zeros(2, dtype=torch.int64, device="cuda")
     b = torch.empty_like(a)
     g = graph_of(torch, lambda: [em.copy_bytes(a, b, 16) for _ in range(nl)])
-    g.replay()
-    ms = tm.per_call_ms(lambda i: g.replay(), reps) / nl
+    for _ in range(warm):
+        g.replay()
+    ms = float(np.median([tm.per_call_ms(lambda i: g.replay(), reps) / nl
+                          for _ in range(trials)]))
     del g
     return ms
 
@@ -1030,9 +1034,6 @@ def main():
            "graph_streams": {str(k): {"ms_per_step": round(v, 5),
                                       "gpx_s": round(H * W / (v * 1e-3) / 1e9, 1)}
                              for k, v in per_streams.items()}}
-    if not args.no_cpu and not args.headline_only:
-        log("timing the CPU oracle")
-        res["cpu_baseline"] = cpu_baseline(img, args.cpu_seconds)
     log("copy ceiling at the headline's byte count")
     copy16 = copy_ceiling(torch, em, tm, 8 << 20, 40, args.steps)
     res["roofline"]["copy_gbs_same_bytes"] = round(copy16, 1)
@@ -1041,6 +1042,10 @@ def main():
     res["roofline"]["launch_floor_us"] = round(floor * 1e3, 2)
     if kernel_ms > floor:     # bandwidth of the part of a launch above the fixed cost
         res["roofline"]["gbs_above_launch_floor"] = round(nbytes / ((kernel_ms - floor) * 1e-3) / 1e9, 1)
+    # after the GPU measurements above: seconds of host-only work let the GPU idle down
+    if not args.no_cpu and not args.headline_only:
+        log("timing the CPU oracle")
+        res["cpu_baseline"] = cpu_baseline(img, args.cpu_seconds)
     if not args.headline_only:
         extra = {}
         extra["copy_ceiling_gbs_1GiB"] = round(copy_ceiling(torch, em, tm, 512 << 20, 2, 20), 1)
