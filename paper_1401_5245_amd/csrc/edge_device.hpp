@@ -83,19 +83,44 @@ struct Geom {
     uint32_t thr;
 };
 
-// Bits 0..3 of the result: bytes 0..3 of `four` >= thr (white pixels).
-__device__ __forceinline__ uint32_t ge_bits4(uint32_t four, uint32_t thr) {
-    uint32_t bits = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) bits |= (((four >> (8 * b)) & 0xffu) >= thr ? 1u : 0u) << b;
-    return bits;
+// Four grey bytes against the threshold at once, in one 32-bit word. With
+// k = 256 - thr, a byte is >= thr exactly when byte + k carries out of its
+// eight bits. The low seven bits of all four bytes are added in one go
+// (their sums stay inside the byte), and the carry out of each byte is the
+// majority of its top bit, k's top bit and the carry into them. Bit 8i + 7
+// of the result is set when byte i >= thr; the other bits are junk. kk is k
+// in every byte and kk7 its low seven bits; thr = 256 gives k = 0 (no byte
+// reaches it), thr = 0 is the caller's (every byte reaches it).
+__device__ __forceinline__ uint32_t ge_top4(uint32_t four, uint32_t kk, uint32_t kk7) {
+    const uint32_t lo = (four & 0x7f7f7f7fu) + kk7;
+    return (four & kk) | ((four | kk) & lo);
 }
 
-// One packed word from 32 grey bytes held in two 128-bit values.
+// Exchange the bits selected by m with those d places above them.
+__device__ __forceinline__ uint32_t swap_bits(uint32_t x, int d, uint32_t m) {
+    const uint32_t t = ((x >> d) ^ x) & m;
+    return x ^ t ^ (t << d);
+}
+
+// One packed word from 32 grey bytes held in two 128-bit values: bit x is
+// white (1) when byte x >= thr (0 <= thr <= 256). Dword m holds pixels
+// 4m..4m+3, each flag at bit 8b + 7 (b = pixel - 4m); shifting dword m's
+// flags down by 7 - m gathers pixel 4m + b at bit 8b + m, and moving every
+// bit from 8b + m to 4m + b (a rotation of the five bit-index bits by two
+// places) takes four exchanges of index bits: 2 and 4, 1 and 3, 0 and 2,
+// 0 and 1. About 55 bitwise operations per word instead of a compare and
+// a select per byte.
 __device__ __forceinline__ uint32_t threshold_word(const u32x4& a, const u32x4& b, uint32_t thr) {
-    return ge_bits4(a.x, thr) | ge_bits4(a.y, thr) << 4 | ge_bits4(a.z, thr) << 8 |
-           ge_bits4(a.w, thr) << 12 | ge_bits4(b.x, thr) << 16 | ge_bits4(b.y, thr) << 20 |
-           ge_bits4(b.z, thr) << 24 | ge_bits4(b.w, thr) << 28;
+    const uint32_t kk = ((256u - thr) & 0xffu) * 0x01010101u, kk7 = kk & 0x7f7f7f7fu;
+    const uint32_t d[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint32_t t = ge_top4(d[7], kk, kk7) & 0x80808080u;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) t |= (ge_top4(d[m], kk, kk7) >> (7 - m)) & (0x01010101u << m);
+    t = swap_bits(t, 12, 0x0000f0f0u);
+    t = swap_bits(t, 6, 0x00cc00ccu);
+    t = swap_bits(t, 3, 0x0a0a0a0au);
+    t = swap_bits(t, 1, 0x22222222u);
+    return thr == 0 ? 0xffffffffu : t;
 }
 
 // ------------------------------------------------------------ word helpers --

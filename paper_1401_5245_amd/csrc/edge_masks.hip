@@ -371,13 +371,6 @@ __global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out
 // packed rows of `stride` 32-bit words out; bits past the width are 0.
 // VEC: the grey pointer and pitch are 16-byte aligned, so full words load
 // their 32 bytes with two 128-bit loads.
-__device__ __forceinline__ uint32_t pack_ge(uint32_t four, uint32_t thr, int shift) {
-    uint32_t bits = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) bits |= (((four >> (8 * b)) & 0xffu) >= thr ? 1u : 0u) << (shift + b);
-    return bits;
-}
-
 template <bool VEC>
 __global__ void __launch_bounds__(256) k_pack(const uint8_t* grey, int64_t gstride, uint32_t* out,
                                               int64_t stride, int32_t height, int32_t width,
@@ -392,9 +385,7 @@ __global__ void __launch_bounds__(256) k_pack(const uint8_t* grey, int64_t gstri
     if (VEC && x0 + 32 <= width) {
         const u32x4 a = *reinterpret_cast<const u32x4*>(rp + x0);
         const u32x4 b = *reinterpret_cast<const u32x4*>(rp + x0 + 16);
-        word = pack_ge(a.x, thr, 0) | pack_ge(a.y, thr, 4) | pack_ge(a.z, thr, 8) |
-               pack_ge(a.w, thr, 12) | pack_ge(b.x, thr, 16) | pack_ge(b.y, thr, 20) |
-               pack_ge(b.z, thr, 24) | pack_ge(b.w, thr, 28);
+        word = threshold_word(a, b, thr);
     } else {
         for (int k = 0; k < 32 && x0 + k < width; ++k)
             word |= (uint32_t)(rp[x0 + k] >= thr) << k;

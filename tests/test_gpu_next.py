@@ -111,6 +111,30 @@ def test_threshold_edges_fused(word_bits, H, W):
                 assert_same(unpack_rows(host, W), want, f"t={t} gs={gs} {border} {mode}")
 
 
+def test_every_threshold_every_byte_value():
+    """Every threshold 0..256 against a grey image that puts every byte
+    value at every bit position of a 32-pixel word (value (x + 37y) mod 256
+    over 32 rows): the whole words take the 128-bit path of both kernels
+    (the first 2048 pixels of a row form a whole chunk of the fused kernel),
+    the last 256 pixels its byte path."""
+    import paper_1401_5245_amd as em
+    H, W = 32, 2304
+    y, x = np.mgrid[0:H, 0:W]
+    grey = ((x + 37 * y) % 256).astype(np.uint8)
+    gt = torch.from_numpy(grey).cuda()
+    S = row_words(W, 64)
+    packed = torch.zeros((H, S), dtype=torch.int64, device="cuda")
+    edges = torch.zeros((H, S), dtype=torch.int64, device="cuda")
+    for t in range(257):
+        em.threshold_pack(gt, packed, H, W, t)
+        em.threshold_edges(gt, edges, H, W, t)
+        torch.cuda.synchronize()
+        binary = oracle.threshold(grey, t)
+        assert_same(unpack_rows(packed.cpu().numpy().view(np.uint64), W), binary, f"pack t={t}")
+        assert_same(unpack_rows(edges.cpu().numpy().view(np.uint64), W), oracle.edge(binary),
+                    f"edges t={t}")
+
+
 @pytest.mark.parametrize("rows,waves,cache", [(1, 1, 1), (3, 2, 2), (16, 8, 1), (64, 4, 2)])
 def test_threshold_edges_cfgs(rows, waves, cache):
     import paper_1401_5245_amd as em
