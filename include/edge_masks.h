@@ -175,8 +175,16 @@ int edge_threshold_pack(const void* grey, int64_t grey_stride_bytes, int thresho
  * is binarised in registers and its edge map (mode, flags and border as
  * for edge_image_launch) written in the packed layout; the binary image is
  * never stored. Equals edge_threshold_pack followed by edge_image_launch.
- * cfg: NULL or a configuration whose vec_words is ignored (one 32-bit word
- * of 32 grey bytes per lane). */
+ * With 16-byte aligned grey rows, every 2048-pixel chunk that lies wholly
+ * inside a row runs as bands: a workgroup of waves_per_block wavefronts
+ * loads waves_per_block x r rows of the chunk at once (r = rows_per_tile
+ * rounded down to 2, 4 or 8, raised until a band loads four rows) and
+ * writes the rows between the first and the last. The rest (a row's last
+ * partial chunk, or unaligned rows) runs as strips of rows_per_tile rows
+ * reading bytes one by one. cfg: NULL for the built-in shapes, or a
+ * configuration for both; vec_words is ignored (one 32-bit word of 32 grey
+ * bytes per lane); cache_policy STREAM makes the bands' loads and stores
+ * non-temporal, AUTO and NORMAL keep them cached. */
 int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int threshold, void* out,
                          int64_t height, int64_t width, int64_t stride_words, int word_bits,
                          int border, int mode, uint32_t flags, const edge_launch_cfg* cfg,

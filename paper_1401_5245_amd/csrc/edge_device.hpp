@@ -263,16 +263,16 @@ __device__ __forceinline__ void store_words(uint32_t* p, const uint32_t (&w)[VW]
 // the load, so the hardware's in-order load counter waits exactly for the
 // row being consumed.
 //
-// GREY (one word per lane): the input is a grey image; each lane reads the
-// 32 bytes of its word, thresholds and packs them in registers, so the
-// binary image never exists in memory (section 7's conversion fused into
-// the edge pass). WHOLE then also means every byte of the span lies inside
-// the row and rows are 16-byte aligned; otherwise bytes load one by one
-// from clamped addresses.
+// GREY (one word per lane, never WHOLE): the input is a grey image; each
+// lane reads the 32 bytes of its word one by one from clamped addresses and
+// thresholds them, so the binary image never exists in memory (section 7's
+// conversion fused into the edge pass). This serves the chunks that the
+// band kernel below does not: a row's last, partial chunk and rows that
+// are not 16-byte aligned.
 template <int VW, int MODE, bool WHOLE, bool EDGES, class Pol, bool GREY = false>
 __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1, uint32_t bw,
                                            bool invert) {
-    static_assert(!GREY || VW == 1, "grey input runs one word per lane");
+    static_assert(!GREY || (VW == 1 && !WHOLE), "grey input: one word per lane, byte loads");
     constexpr int P = Pol::prefetch;
     const int lane = threadIdx.x & (kWave - 1);
     const int jl = j0 + lane * VW;
@@ -296,7 +296,7 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
     const uint32_t vme = valid_bits(je, g.width), ome = bw & ~vme;
 
     struct RawPacked { uint32_t w[VW]; uint32_t e; };
-    struct RawGrey { u32x4 b[2]; uint32_t e; };
+    struct RawGrey { uint32_t word, e; };
     using Raw = std::conditional_t<GREY, RawGrey, RawPacked>;
     struct Row { uint32_t c[VW], w[VW], e[VW]; };
     // grey input: the neighbour pixel just outside the span (its byte)
@@ -307,20 +307,12 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
         Raw r;
         if constexpr (GREY) {
             const uint8_t* rp = g.grey + (int64_t)yc * g.grey_stride;
-            if constexpr (WHOLE) {
-                const u32x4* vp = reinterpret_cast<const u32x4*>(rp + 32ll * jl);
-                r.b[0] = Pol::nt_load ? __builtin_nontemporal_load(vp) : vp[0];
-                r.b[1] = Pol::nt_load ? __builtin_nontemporal_load(vp + 1) : vp[1];
-            } else {
-                // byte by byte from clamped addresses, thresholded at once
-                // (the packed word goes in b[0].x)
-                uint32_t word = 0;
+            // byte by byte from clamped addresses, thresholded at once
+            r.word = 0;
 #pragma unroll
-                for (int k = 0; k < 32; ++k) {
-                    const int64_t x = 32ll * jl + k;
-                    word |= (uint32_t)(rp[x < g.width ? x : g.width - 1] >= g.thr) << k;
-                }
-                r.b[0].x = word;
+            for (int k = 0; k < 32; ++k) {
+                const int64_t x = 32ll * jl + k;
+                r.word |= (uint32_t)(rp[x < g.width ? x : g.width - 1] >= g.thr) << k;
             }
             if constexpr (EDGES) r.e = rp[has_e ? xe_load : 0];
             else r.e = 0;
@@ -347,8 +339,7 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
         Row o;
         uint32_t e;
         if constexpr (GREY) {
-            const uint32_t word = WHOLE ? threshold_word(r.b[0], r.b[1], g.thr) : r.b[0].x;
-            o.c[0] = inside ? ((word & vm[0]) | om[0]) : bw;
+            o.c[0] = inside ? ((r.word & vm[0]) | om[0]) : bw;
             // only the neighbour pixel's bit is used by the carries
             e = (EDGES && inside && has_e) ? (r.e >= g.thr ? 0xffffffffu : 0u) : bw;
         } else {
@@ -442,23 +433,93 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
     }
 }
 
-// Grey input (threshold then edges), one word per lane. TAIL = false: the
-// span's bytes all lie in the row and rows are 16-byte aligned (128-bit
-// loads); TAIL = true: bytes load one by one from clamped addresses, with
-// one row in flight (the row's last chunk, or unaligned rows). The two run
-// as separate launches so the byte path does not set the register budget of
-// the aligned one.
-template <int MODE, class Pol, bool TAIL>
-__device__ __forceinline__ void grey_strip_unit(const Geom& g, int j0, int y0, int y1,
-                                                uint32_t bw, bool invert) {
+// Grey input (threshold then edges) on the byte path, one word per lane:
+// the chunks the band kernel does not take, with one row in flight.
+template <int MODE>
+__device__ __forceinline__ void grey_tail_unit(const Geom& g, int j0, int y0, int y1, uint32_t bw,
+                                               bool invert) {
     using Tail = StripPolicy<1, false, false>;
-    const bool edges = j0 > 0 || j0 + kWave < g.wd;
-    if constexpr (!TAIL) {
-        if (edges) strip_body<1, MODE, true, true, Pol, true>(g, j0, y0, y1, bw, invert);
-        else strip_body<1, MODE, true, false, Pol, true>(g, j0, y0, y1, bw, invert);
-    } else {
-        if (edges) strip_body<1, MODE, false, true, Tail, true>(g, j0, y0, y1, bw, invert);
-        else strip_body<1, MODE, false, false, Tail, true>(g, j0, y0, y1, bw, invert);
+    if (j0 > 0 || j0 + kWave < g.wd) strip_body<1, MODE, false, true, Tail, true>(g, j0, y0, y1, bw, invert);
+    else strip_body<1, MODE, false, false, Tail, true>(g, j0, y0, y1, bw, invert);
+}
+
+// Grey input over whole chunks, as bands. A workgroup of nw wavefronts
+// loads the nw * RW consecutive rows y0 - 1 .. y0 + nw * RW - 2 of one
+// 64-word chunk, every row's 32 bytes per lane in flight at once,
+// thresholds them into packed words in LDS, and then computes the
+// nw * RW - 2 rows between the first and the last from LDS. Concurrent
+// workgroups take consecutive chunks and bands, so the rows in flight form
+// one compact window of the image; a wavefront walking a long strip of
+// its own keeps its next rows in flight at a different place of the image
+// from every other, which measured slower for grey rows (32 bytes per lane
+// and row, eight times a packed row). An LDS row holds, in this order, the
+// pixel left of the chunk (replicated over the word), the 64 words and the
+// pixel right of it, so the west and east neighbour words of every lane
+// come from LDS. Every pixel of a whole chunk lies inside the row.
+constexpr int kBandPitch = kWave + 2;
+
+template <int MODE, int RW, class Pol>
+__device__ __forceinline__ void grey_band_unit(const Geom& g, uint32_t* tile, int nw, int j0,
+                                               int64_t y0, uint32_t bw, bool invert) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = wave_uniform(threadIdx.x / kWave);
+    const int jl = j0 + lane;
+    const int64_t xl = 32ll * j0 - 1, xr = 32ll * (j0 + kWave);
+    const bool has_l = j0 > 0, has_r = xr < g.width;
+    const bool edge_lane = lane == 0 || lane == kWave - 1;
+    const int64_t xe = lane == 0 ? (has_l ? xl : 0) : (has_r ? xr : 0);
+
+    u32x4 a[RW], b[RW];
+    uint32_t eb[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const int64_t y = y0 - 1 + i * nw + w;
+        const int64_t yc = y < 0 ? 0 : (y >= g.height ? g.height - 1 : y);
+        const uint8_t* rp = g.grey + yc * g.grey_stride;
+        const u32x4* vp = reinterpret_cast<const u32x4*>(rp + 32ll * jl);
+        a[i] = Pol::nt_load ? __builtin_nontemporal_load(vp) : vp[0];
+        b[i] = Pol::nt_load ? __builtin_nontemporal_load(vp + 1) : vp[1];
+        eb[i] = edge_lane ? rp[xe] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const int l = i * nw + w;
+        const int64_t y = y0 - 1 + l;
+        const bool inside = y >= 0 && y < g.height;
+        uint32_t* t = tile + l * kBandPitch;
+        t[1 + lane] = inside ? threshold_word(a[i], b[i], g.thr) : bw;
+        const uint32_t side = eb[i] >= g.thr ? 0xffffffffu : 0u;
+        if (lane == 0) t[0] = inside && has_l ? side : bw;
+        if (lane == kWave - 1) t[kBandPitch - 1] = inside && has_r ? side : bw;
+    }
+    __syncthreads();
+
+    // output rows y0 + o, o = 0 .. nw * RW - 3; wavefront w takes a
+    // contiguous share
+    const int ob = nw * RW - 2;
+    const int o0 = w * ob / nw, o1 = (w + 1) * ob / nw;
+    auto row = [&](int l, uint32_t& c, uint32_t& wv, uint32_t& ev) {
+        const uint32_t* t = tile + l * kBandPitch + lane;
+        c = t[1];
+        wv = west_of(c, t[0]);
+        ev = east_of(c, t[2]);
+    };
+    uint32_t uc, uw, ue, cc, cw, ce;
+    row(o0, uc, uw, ue);
+    row(o0 + 1, cc, cw, ce);
+    for (int o = o0; o < o1; ++o) {
+        uint32_t dc, dw, de;
+        row(o + 2, dc, dw, de);
+        const int64_t y = y0 + o;
+        if (y < g.height) {
+            const uint32_t v = edge_word<MODE>(cc, ue, uc, uw, cw, dw, dc, de, ce);
+            uint32_t* op = g.out + y * g.stride + jl;
+            const uint32_t res = invert ? ~v : v;
+            if constexpr (Pol::nt_store) __builtin_nontemporal_store(res, op);
+            else *op = res;
+        }
+        uc = cc; uw = cw; ue = ce;
+        cc = dc; cw = dw; ce = de;
     }
 }
 

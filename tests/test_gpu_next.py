@@ -135,6 +135,36 @@ def test_every_threshold_every_byte_value():
                     f"edges t={t}")
 
 
+@pytest.mark.parametrize("waves,rows", [(1, 1), (1, 8), (2, 2), (2, 4), (4, 4), (4, 8), (8, 2),
+                                       (8, 8)])
+def test_threshold_edges_band_heights(waves, rows):
+    """Whole chunks run as bands of waves * rows' loaded rows (rows rounded
+    to 2, 4 or 8, at least four rows a band) less two: heights around one
+    and two bands, in every mode, with and without a byte-path tail."""
+    import paper_1401_5245_amd as em
+    rw = 8 if rows >= 8 else (4 if rows >= 4 else 2)
+    while waves * rw < 4:
+        rw *= 2
+    ob = waves * rw - 2
+    cfg = dict(vec_words=1, rows_per_tile=rows, waves_per_block=waves, cache_policy=1)
+    for H in sorted({1, 2, 3, ob - 1, ob, ob + 1, 2 * ob - 1, 2 * ob + 1} - {0}):
+        for W in (2048, 4096 + 37):
+            grey = images.grey_image(H, W, seed=H * 3 + W + waves)
+            gt = torch.from_numpy(np.ascontiguousarray(grey)).cuda()
+            binary = oracle.threshold(grey, 128)
+            for border, mode, c2, inv in (("white", "masks", False, False),
+                                          ("black", "full", False, True),
+                                          ("white", "full", True, False)):
+                out = torch.full((H, row_words(W, 64)), -1, dtype=torch.int64, device="cuda")
+                em.threshold_edges(gt, out, H, W, 128, border=border, mode=mode,
+                                   clause2_only=c2, invert=inv, cfg=cfg)
+                torch.cuda.synchronize()
+                clauses = oracle.CLAUSE2 if c2 else (3 if mode == "full" else oracle.CLAUSE1)
+                want = oracle.edge(binary, border=border, clauses=clauses, invert=inv)
+                assert_same(unpack_rows(out.cpu().numpy().view(np.uint64), W), want,
+                            f"H={H} W={W} {border} {mode} c2={c2}")
+
+
 @pytest.mark.parametrize("rows,waves,cache", [(1, 1, 1), (3, 2, 2), (16, 8, 1), (64, 4, 2)])
 def test_threshold_edges_cfgs(rows, waves, cache):
     import paper_1401_5245_amd as em
