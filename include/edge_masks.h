@@ -166,7 +166,10 @@ int edge_directions(const void* in, void* out4, int64_t plane_words, int64_t hei
  * (1), a smaller one black (0); threshold 0..256 (0: all white, 256: all
  * black). out: packed rows in the layout above (stride_words words of
  * word_bits), bits past the width written 0, stride words untouched.
- * 16-byte aligned grey rows load 128 bits at a time. */
+ * Any pointer and pitch: bytes load in the 16-byte aligned blocks that hold
+ * them (two per 32 pixels where rows start on 16-byte boundaries, three
+ * otherwise); a block can reach up to 15 bytes before a row's first byte
+ * or after its last, never outside the memory pages of the row. */
 int edge_threshold_pack(const void* grey, int64_t grey_stride_bytes, int threshold, void* out,
                         int64_t height, int64_t width, int64_t stride_words, int word_bits,
                         void* hip_stream);
@@ -175,15 +178,13 @@ int edge_threshold_pack(const void* grey, int64_t grey_stride_bytes, int thresho
  * is binarised in registers and its edge map (mode, flags and border as
  * for edge_image_launch) written in the packed layout; the binary image is
  * never stored. Equals edge_threshold_pack followed by edge_image_launch.
- * With 16-byte aligned grey rows, every 2048-pixel chunk that lies wholly
- * inside a row runs as bands: a workgroup of waves_per_block wavefronts
- * loads waves_per_block x r rows of the chunk at once (r = rows_per_tile
- * rounded down to 2, 4 or 8, raised until a band loads four rows) and
- * writes the rows between the first and the last. The rest (a row's last
- * partial chunk, or unaligned rows) runs as strips of rows_per_tile rows
- * reading bytes one by one. cfg: NULL for the built-in shapes, or a
- * configuration for both; vec_words is ignored (one 32-bit word of 32 grey
- * bytes per lane); cache_policy STREAM makes the bands' loads and stores
+ * Grey bytes load as for edge_threshold_pack. The image runs as bands of
+ * 2048-pixel chunks: a workgroup of waves_per_block wavefronts loads
+ * waves_per_block x r rows of a chunk at once (r = rows_per_tile rounded
+ * down to 2, 4 or 8, raised until a band loads four rows) and writes the
+ * rows between the first and the last. cfg: NULL for the built-in shape
+ * (8 wavefronts, r = 2, cached), or a configuration; vec_words and
+ * blocks_per_cu are ignored; cache_policy STREAM makes the loads and stores
  * non-temporal, AUTO and NORMAL keep them cached. */
 int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int threshold, void* out,
                          int64_t height, int64_t width, int64_t stride_words, int word_bits,

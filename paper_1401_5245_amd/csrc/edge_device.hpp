@@ -77,7 +77,7 @@ struct Geom {
     int32_t wd;       // words per row the kernels touch (whole B-bit words)
     int64_t plane;    // words between output planes (kModeDirections only)
     // grey input (threshold then edges): rows of grey_stride bytes; a byte
-    // >= thr is white. Used when the strip runs with GREY set.
+    // >= thr is white. Used by the grey kernels.
     const uint8_t* grey;
     int64_t grey_stride;
     uint32_t thr;
@@ -121,6 +121,72 @@ __device__ __forceinline__ uint32_t threshold_word(const u32x4& a, const u32x4& 
     t = swap_bits(t, 3, 0x0a0a0a0au);
     t = swap_bits(t, 1, 0x22222222u);
     return thr == 0 ? 0xffffffffu : t;
+}
+
+// The 32 grey bytes of packed word j of a row, as 16-byte blocks counted
+// from the 16-byte boundary at or before the row start (r = the row
+// start's offset from it): block b starts 32j + 16b bytes after that
+// boundary, clamped to the row's last block, so every block loaded holds at
+// least one byte of the row and lies in the same memory page as that byte
+// (no load can fault, whatever the row's alignment or the word's place).
+// Bytes at or past the width come out as junk bits that the caller masks.
+// ALIGNED (r = 0): the word is two blocks; otherwise three, and the word's
+// bytes start r bytes into the first.
+template <bool ALIGNED>
+struct GreyBlocks {
+    u32x4 q[ALIGNED ? 2 : 3];
+};
+
+template <bool ALIGNED, bool NT>
+__device__ __forceinline__ GreyBlocks<ALIGNED> load_grey_word(const uint8_t* row, int j,
+                                                              int32_t width) {
+    const uint32_t r = ALIGNED ? 0u : (uint32_t)((uintptr_t)row & 15u);
+    const uint8_t* base = row - r;
+    const uint32_t last = (r + (uint32_t)width - 1u) & ~15u;
+    GreyBlocks<ALIGNED> gb;
+#pragma unroll
+    for (int b = 0; b < (ALIGNED ? 2 : 3); ++b) {
+        uint32_t off = 32u * (uint32_t)j + 16u * b;
+        off = off < last ? off : last;
+        const u32x4* p = reinterpret_cast<const u32x4*>(base + off);
+        gb.q[b] = NT ? __builtin_nontemporal_load(p) : *p;
+    }
+    return gb;
+}
+
+// The packed word of unaligned blocks whose word starts QD dwords and rb
+// bytes into the first block: each of its dwords is a funnel of two loaded
+// neighbours (constant indices, so the blocks stay in registers).
+template <int QD>
+__device__ __forceinline__ uint32_t grey_word_at(const GreyBlocks<false>& gb, uint32_t rb,
+                                                 uint32_t thr) {
+    const uint32_t d[12] = {gb.q[0].x, gb.q[0].y, gb.q[0].z, gb.q[0].w,
+                            gb.q[1].x, gb.q[1].y, gb.q[1].z, gb.q[1].w,
+                            gb.q[2].x, gb.q[2].y, gb.q[2].z, gb.q[2].w};
+    uint32_t o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = __builtin_amdgcn_alignbyte(d[QD + k + 1], d[QD + k], rb);
+    const u32x4 a = {o[0], o[1], o[2], o[3]}, b = {o[4], o[5], o[6], o[7]};
+    return threshold_word(a, b, thr);
+}
+
+// The packed word of those blocks (bit k: byte 32j + k >= thr). Unaligned:
+// the word starts r bytes into the first block, r being the same for every
+// lane of a row (so the switch is uniform).
+template <bool ALIGNED>
+__device__ __forceinline__ uint32_t grey_word(const GreyBlocks<ALIGNED>& gb, const uint8_t* row,
+                                              uint32_t thr) {
+    if constexpr (ALIGNED) {
+        return threshold_word(gb.q[0], gb.q[1], thr);
+    } else {
+        const uint32_t r = (uint32_t)((uintptr_t)row & 15u), rb = r & 3u;
+        switch (r >> 2) {
+            case 0: return grey_word_at<0>(gb, rb, thr);
+            case 1: return grey_word_at<1>(gb, rb, thr);
+            case 2: return grey_word_at<2>(gb, rb, thr);
+            default: return grey_word_at<3>(gb, rb, thr);
+        }
+    }
 }
 
 // ------------------------------------------------------------ word helpers --
@@ -262,17 +328,9 @@ __device__ __forceinline__ void store_words(uint32_t* p, const uint32_t (&w)[VW]
 // outside the image are clamped into it and replaced by the border after
 // the load, so the hardware's in-order load counter waits exactly for the
 // row being consumed.
-//
-// GREY (one word per lane, never WHOLE): the input is a grey image; each
-// lane reads the 32 bytes of its word one by one from clamped addresses and
-// thresholds them, so the binary image never exists in memory (section 7's
-// conversion fused into the edge pass). This serves the chunks that the
-// band kernel below does not: a row's last, partial chunk and rows that
-// are not 16-byte aligned.
-template <int VW, int MODE, bool WHOLE, bool EDGES, class Pol, bool GREY = false>
+template <int VW, int MODE, bool WHOLE, bool EDGES, class Pol>
 __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1, uint32_t bw,
                                            bool invert) {
-    static_assert(!GREY || (VW == 1 && !WHOLE), "grey input: one word per lane, byte loads");
     constexpr int P = Pol::prefetch;
     const int lane = threadIdx.x & (kWave - 1);
     const int jl = j0 + lane * VW;
@@ -295,38 +353,21 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
     const int je_load = has_e ? je : j0;
     const uint32_t vme = valid_bits(je, g.width), ome = bw & ~vme;
 
-    struct RawPacked { uint32_t w[VW]; uint32_t e; };
-    struct RawGrey { uint32_t word, e; };
-    using Raw = std::conditional_t<GREY, RawGrey, RawPacked>;
+    struct Raw { uint32_t w[VW]; uint32_t e; };
     struct Row { uint32_t c[VW], w[VW], e[VW]; };
-    // grey input: the neighbour pixel just outside the span (its byte)
-    const int64_t xe_load = lane == 0 ? 32ll * j0 - 1 : 32ll * (j0 + kWave);
 
     auto load_raw = [&](int y) {
         const int yc = y < 0 ? 0 : (y >= g.height ? g.height - 1 : y);
         Raw r;
-        if constexpr (GREY) {
-            const uint8_t* rp = g.grey + (int64_t)yc * g.grey_stride;
-            // byte by byte from clamped addresses, thresholded at once
-            r.word = 0;
-#pragma unroll
-            for (int k = 0; k < 32; ++k) {
-                const int64_t x = 32ll * jl + k;
-                r.word |= (uint32_t)(rp[x < g.width ? x : g.width - 1] >= g.thr) << k;
-            }
-            if constexpr (EDGES) r.e = rp[has_e ? xe_load : 0];
-            else r.e = 0;
+        const uint32_t* rp = g.in + (int64_t)yc * g.stride;
+        if constexpr (WHOLE) {
+            load_words<VW, Pol::nt_load>(rp + jl, r.w);
         } else {
-            const uint32_t* rp = g.in + (int64_t)yc * g.stride;
-            if constexpr (WHOLE) {
-                load_words<VW, Pol::nt_load>(rp + jl, r.w);
-            } else {
 #pragma unroll
-                for (int k = 0; k < VW; ++k) r.w[k] = rp[jw[k]];
-            }
-            if constexpr (EDGES) r.e = rp[je_load];
-            else r.e = bw;
+            for (int k = 0; k < VW; ++k) r.w[k] = rp[jw[k]];
         }
+        if constexpr (EDGES) r.e = rp[je_load];
+        else r.e = bw;
         return r;
     };
 
@@ -337,16 +378,9 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
     auto shift_row = [&](const Raw& r, int y) {
         const bool inside = (unsigned)y < (unsigned)g.height;
         Row o;
-        uint32_t e;
-        if constexpr (GREY) {
-            o.c[0] = inside ? ((r.word & vm[0]) | om[0]) : bw;
-            // only the neighbour pixel's bit is used by the carries
-            e = (EDGES && inside && has_e) ? (r.e >= g.thr ? 0xffffffffu : 0u) : bw;
-        } else {
 #pragma unroll
-            for (int k = 0; k < VW; ++k) o.c[k] = inside ? ((r.w[k] & vm[k]) | om[k]) : bw;
-            e = (EDGES && inside && has_e) ? ((r.e & vme) | ome) : bw;
-        }
+        for (int k = 0; k < VW; ++k) o.c[k] = inside ? ((r.w[k] & vm[k]) | om[k]) : bw;
+        const uint32_t e = (EDGES && inside && has_e) ? ((r.e & vme) | ome) : bw;
         const uint32_t left = from_lower_lane(o.c[VW - 1], e);
         const uint32_t right = from_upper_lane(o.c[0], e);
 #pragma unroll
@@ -433,61 +467,53 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
     }
 }
 
-// Grey input (threshold then edges) on the byte path, one word per lane:
-// the chunks the band kernel does not take, with one row in flight.
-template <int MODE>
-__device__ __forceinline__ void grey_tail_unit(const Geom& g, int j0, int y0, int y1, uint32_t bw,
-                                               bool invert) {
-    using Tail = StripPolicy<1, false, false>;
-    if (j0 > 0 || j0 + kWave < g.wd) strip_body<1, MODE, false, true, Tail, true>(g, j0, y0, y1, bw, invert);
-    else strip_body<1, MODE, false, false, Tail, true>(g, j0, y0, y1, bw, invert);
-}
-
-// Grey input over whole chunks, as bands. A workgroup of nw wavefronts
-// loads the nw * RW consecutive rows y0 - 1 .. y0 + nw * RW - 2 of one
-// 64-word chunk, every row's 32 bytes per lane in flight at once,
-// thresholds them into packed words in LDS, and then computes the
-// nw * RW - 2 rows between the first and the last from LDS. Concurrent
-// workgroups take consecutive chunks and bands, so the rows in flight form
-// one compact window of the image; a wavefront walking a long strip of
-// its own keeps its next rows in flight at a different place of the image
-// from every other, which measured slower for grey rows (32 bytes per lane
-// and row, eight times a packed row). An LDS row holds, in this order, the
-// pixel left of the chunk (replicated over the word), the 64 words and the
-// pixel right of it, so the west and east neighbour words of every lane
-// come from LDS. Every pixel of a whole chunk lies inside the row.
+// Grey input as bands (section 7's threshold fused into the edge pass; the
+// binary image is never stored). A workgroup of nw wavefronts loads the
+// nw * RW consecutive rows y0 - 1 .. y0 + nw * RW - 2 of one 64-word chunk,
+// every row's 32 bytes per lane in flight at once, thresholds them into
+// packed words in LDS, and then computes the nw * RW - 2 rows between the
+// first and the last from LDS. Concurrent workgroups take consecutive
+// chunks and bands, so the rows in flight form one compact window of the
+// image; a wavefront walking a long strip of its own keeps its next rows
+// in flight at a different place of the image from every other, which
+// measured slower for grey rows (32 bytes per lane and row, eight times a
+// packed row). An LDS row holds, in this order, the pixel left of the chunk
+// (replicated over the word), the 64 words and the pixel right of it, so
+// the west and east neighbour words of every lane come from LDS. Words
+// past the row end hold the border colour, pad bits too.
 constexpr int kBandPitch = kWave + 2;
 
-template <int MODE, int RW, class Pol>
+template <int MODE, int RW, bool ALIGNED, class Pol>
 __device__ __forceinline__ void grey_band_unit(const Geom& g, uint32_t* tile, int nw, int j0,
                                                int64_t y0, uint32_t bw, bool invert) {
     const int lane = threadIdx.x & (kWave - 1);
     const int w = wave_uniform(threadIdx.x / kWave);
     const int jl = j0 + lane;
+    const uint32_t vm = valid_bits(jl, g.width), om = bw & ~vm;
     const int64_t xl = 32ll * j0 - 1, xr = 32ll * (j0 + kWave);
     const bool has_l = j0 > 0, has_r = xr < g.width;
     const bool edge_lane = lane == 0 || lane == kWave - 1;
     const int64_t xe = lane == 0 ? (has_l ? xl : 0) : (has_r ? xr : 0);
 
-    u32x4 a[RW], b[RW];
+    GreyBlocks<ALIGNED> q[RW];
     uint32_t eb[RW];
 #pragma unroll
     for (int i = 0; i < RW; ++i) {
         const int64_t y = y0 - 1 + i * nw + w;
         const int64_t yc = y < 0 ? 0 : (y >= g.height ? g.height - 1 : y);
         const uint8_t* rp = g.grey + yc * g.grey_stride;
-        const u32x4* vp = reinterpret_cast<const u32x4*>(rp + 32ll * jl);
-        a[i] = Pol::nt_load ? __builtin_nontemporal_load(vp) : vp[0];
-        b[i] = Pol::nt_load ? __builtin_nontemporal_load(vp + 1) : vp[1];
+        q[i] = load_grey_word<ALIGNED, Pol::nt_load>(rp, jl, g.width);
         eb[i] = edge_lane ? rp[xe] : 0u;
     }
 #pragma unroll
     for (int i = 0; i < RW; ++i) {
         const int l = i * nw + w;
         const int64_t y = y0 - 1 + l;
+        const int64_t yc = y < 0 ? 0 : (y >= g.height ? g.height - 1 : y);
         const bool inside = y >= 0 && y < g.height;
         uint32_t* t = tile + l * kBandPitch;
-        t[1 + lane] = inside ? threshold_word(a[i], b[i], g.thr) : bw;
+        const uint32_t word = grey_word<ALIGNED>(q[i], g.grey + yc * g.grey_stride, g.thr);
+        t[1 + lane] = inside ? ((word & vm) | om) : bw;
         const uint32_t side = eb[i] >= g.thr ? 0xffffffffu : 0u;
         if (lane == 0) t[0] = inside && has_l ? side : bw;
         if (lane == kWave - 1) t[kBandPitch - 1] = inside && has_r ? side : bw;
@@ -511,10 +537,10 @@ __device__ __forceinline__ void grey_band_unit(const Geom& g, uint32_t* tile, in
         uint32_t dc, dw, de;
         row(o + 2, dc, dw, de);
         const int64_t y = y0 + o;
-        if (y < g.height) {
-            const uint32_t v = edge_word<MODE>(cc, ue, uc, uw, cw, dw, dc, de, ce);
+        if (y < g.height && jl < g.wd) {
+            const uint32_t v = edge_word<MODE>(cc, ue, uc, uw, cw, dw, dc, de, ce) & vm;
             uint32_t* op = g.out + y * g.stride + jl;
-            const uint32_t res = invert ? ~v : v;
+            const uint32_t res = invert ? (v ^ vm) : v;
             if constexpr (Pol::nt_store) __builtin_nontemporal_store(res, op);
             else *op = res;
         }

@@ -36,37 +36,22 @@ __global__ void __launch_bounds__(512) k_strip(Geom g, int64_t chunks, int rows,
     strip_unit<VW, MODE, Pol>(g, (int)(chunk * kWave * VW), (int)y0, (int)y1, bw, invert != 0);
 }
 
-// Grey image in, edge map out (threshold fused into the strip's byte
-// loads), over word chunks [chunk0, chunk0 + chunks) of every row: the
-// chunks that do not run as bands.
-template <int MODE>
-__global__ void __launch_bounds__(512) k_grey_tail(Geom g, int64_t chunk0, int64_t chunks,
-                                                   int rows, int64_t nunits, uint32_t bw,
-                                                   int invert) {
-    const int wpb = blockDim.x / kWave;
-    const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
-                         wave_uniform(threadIdx.x / kWave);
-    if (unit >= nunits) return;
-    const int64_t strip = unit / chunks;
-    const int64_t chunk = chunk0 + (unit - strip * chunks);
-    const int64_t y0 = strip * rows;
-    const int64_t y1 = y0 + rows < g.height ? y0 + rows : g.height;
-    grey_tail_unit<MODE>(g, (int)(chunk * kWave), (int)y0, (int)y1, bw, invert != 0);
-}
-
-// Grey image in, edge map out, over whole chunks: one workgroup per band
-// of nw * RW - 2 output rows of one chunk.
-template <int MODE, int RW, class Pol>
+// Grey image in, edge map out: units are bands of nw * RW - 2 output rows
+// of one 64-word chunk, one per workgroup; a grid smaller than the unit
+// count (very tall images) takes them in turns, the LDS tile reused after
+// a barrier.
+template <int MODE, int RW, bool ALIGNED, class Pol>
 __global__ void __launch_bounds__(512) k_grey_band(Geom g, int64_t chunks, int64_t nunits,
                                                    uint32_t bw, int invert) {
     extern __shared__ uint32_t band_tile[];
     const int nw = blockDim.x / kWave;
-    const int64_t unit = xcd_block(blockIdx.x, gridDim.x);
-    if (unit >= nunits) return;
-    const int64_t band = unit / chunks;
-    const int64_t chunk = unit - band * chunks;
-    grey_band_unit<MODE, RW, Pol>(g, band_tile, nw, (int)(chunk * kWave),
-                                  band * (nw * RW - 2), bw, invert != 0);
+    for (int64_t unit = xcd_block(blockIdx.x, gridDim.x); unit < nunits; unit += gridDim.x) {
+        const int64_t band = unit / chunks;
+        const int64_t chunk = unit - band * chunks;
+        grey_band_unit<MODE, RW, ALIGNED, Pol>(g, band_tile, nw, (int)(chunk * kWave),
+                                               band * (nw * RW - 2), bw, invert != 0);
+        if (unit + gridDim.x < nunits) __syncthreads();
+    }
 }
 
 // Iterated peeling of one image: strips of `rows` rows x kPeelSpan words,
@@ -381,12 +366,11 @@ __global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out
 }
 
 // Threshold binarisation + packing (section 7: a grey image is first made
-// binary by a threshold): one 32-bit output word per thread, from 32 grey
-// bytes; a byte >= thr becomes white (1). Rows of `gstride` bytes in,
-// packed rows of `stride` 32-bit words out; bits past the width are 0.
-// VEC: the grey pointer and pitch are 16-byte aligned, so full words load
-// their 32 bytes with two 128-bit loads.
-template <bool VEC>
+// binary by a threshold): one 32-bit output word per thread, from the 16-byte
+// blocks that hold its 32 grey bytes; a byte >= thr becomes white (1). Rows
+// of `gstride` bytes in, packed rows of `stride` 32-bit words out; bits past
+// the width are 0. ALIGNED: the grey pointer and pitch are 16-byte aligned.
+template <bool ALIGNED>
 __global__ void __launch_bounds__(256) k_pack(const uint8_t* grey, int64_t gstride, uint32_t* out,
                                               int64_t stride, int32_t height, int32_t width,
                                               int32_t wd, uint32_t thr) {
@@ -395,17 +379,8 @@ __global__ void __launch_bounds__(256) k_pack(const uint8_t* grey, int64_t gstri
     const int64_t y = t / wd;
     const int j = (int)(t - y * wd);
     const uint8_t* rp = grey + y * gstride;
-    const int64_t x0 = 32ll * j;
-    uint32_t word = 0;
-    if (VEC && x0 + 32 <= width) {
-        const u32x4 a = *reinterpret_cast<const u32x4*>(rp + x0);
-        const u32x4 b = *reinterpret_cast<const u32x4*>(rp + x0 + 16);
-        word = threshold_word(a, b, thr);
-    } else {
-        for (int k = 0; k < 32 && x0 + k < width; ++k)
-            word |= (uint32_t)(rp[x0 + k] >= thr) << k;
-    }
-    out[y * stride + j] = word;
+    const GreyBlocks<ALIGNED> q = load_grey_word<ALIGNED, false>(rp, j, width);
+    out[y * stride + j] = grey_word<ALIGNED>(q, rp, thr) & valid_bits(j, width);
 }
 
 // The paper's method as separate whole-image passes (sections 3-5), each a
@@ -810,59 +785,50 @@ struct EdgeGraph {
     hipGraphExec_t exec;
 };
 
-template <int MODE>
-int launch_grey_tail(const Geom& g, const edge_launch_cfg& c, int64_t chunk0, int64_t chunks,
-                     uint32_t bw, int invert, hipStream_t stream) {
-    if (chunks <= 0) return EDGE_OK;
-    const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
-    const int64_t blocks = ceil_div(nunits, c.waves_per_block);
-    if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL((k_grey_tail<MODE>), dim3((uint32_t)blocks), dim3(c.waves_per_block * kWave),
-                       0, stream, g, chunk0, chunks, c.rows_per_tile, nunits, bw, invert);
-    return launch_status();
-}
+// Workgroups of one grey-band launch at most (2^22 x 512 threads stays
+// below the grid's 2^32 threads); beyond, each takes several bands.
+constexpr int64_t kMaxBandBlocks = int64_t(1) << 22;
 
-template <int MODE, int RW, class Pol>
-int launch_grey_band_rw(const Geom& g, int nw, int64_t whole, uint32_t bw, int invert,
+template <int MODE, int RW, bool ALIGNED, class Pol>
+int launch_grey_band_rw(const Geom& g, int nw, int64_t chunks, uint32_t bw, int invert,
                         hipStream_t stream) {
-    const int64_t nunits = whole * ceil_div(g.height, (int64_t)(nw * RW - 2));
-    if (!grid_fits(nunits, nw * kWave)) return EDGE_ERR_UNSUPPORTED;
+    const int64_t nunits = chunks * ceil_div(g.height, (int64_t)(nw * RW - 2));
+    const int64_t blocks = std::min<int64_t>(nunits, kMaxBandBlocks);
     const size_t lds = (size_t)nw * RW * kBandPitch * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_grey_band<MODE, RW, Pol>), dim3((uint32_t)nunits), dim3(nw * kWave),
-                       lds, stream, g, whole, nunits, bw, invert);
+    hipLaunchKernelGGL((k_grey_band<MODE, RW, ALIGNED, Pol>), dim3((uint32_t)blocks),
+                       dim3(nw * kWave), lds, stream, g, chunks, nunits, bw, invert);
     return launch_status();
 }
 
 // Band shape from the launch shape: waves_per_block wavefronts, each
 // loading rows_per_tile rows rounded down to 2, 4 or 8 (a band loads at
 // least four rows).
-template <int MODE, class Pol>
-int launch_grey_band(const Geom& g, const edge_launch_cfg& c, int64_t whole, uint32_t bw,
-                     int invert, hipStream_t stream) {
-    if (whole <= 0) return EDGE_OK;
+template <int MODE, bool ALIGNED, class Pol>
+int launch_grey_band(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int invert,
+                     hipStream_t stream) {
+    const int64_t chunks = ceil_div(g.wd, (int64_t)kWave);
     const int nw = c.waves_per_block;
     int rw = c.rows_per_tile >= 8 ? 8 : (c.rows_per_tile >= 4 ? 4 : 2);
     while (nw * rw < 4) rw *= 2;
-    if (rw == 8) return launch_grey_band_rw<MODE, 8, Pol>(g, nw, whole, bw, invert, stream);
-    if (rw == 4) return launch_grey_band_rw<MODE, 4, Pol>(g, nw, whole, bw, invert, stream);
-    return launch_grey_band_rw<MODE, 2, Pol>(g, nw, whole, bw, invert, stream);
+    if (rw == 8) return launch_grey_band_rw<MODE, 8, ALIGNED, Pol>(g, nw, chunks, bw, invert, stream);
+    if (rw == 4) return launch_grey_band_rw<MODE, 4, ALIGNED, Pol>(g, nw, chunks, bw, invert, stream);
+    return launch_grey_band_rw<MODE, 2, ALIGNED, Pol>(g, nw, chunks, bw, invert, stream);
 }
 
-// Chunks whose 64 words of grey bytes lie wholly inside the row (and rows
-// 16-byte aligned) run as bands with 128-bit loads; the rest take the byte
-// path. Streaming (non-temporal) loads and stores only when asked for:
-// bands re-read their first and last rows from the cache, and cached was
-// faster at every size measured (8192^2 to 65536^2).
+// Rows that start on 16-byte boundaries (pointer and pitch) load two
+// blocks per word, others three. Streaming (non-temporal) loads and stores
+// only when asked for: bands re-read their first and last rows from the
+// cache, and cached was faster at every size measured (8192^2 to 65536^2).
 template <int MODE>
-int launch_grey(const Geom& g, const edge_launch_cfg& band, const edge_launch_cfg& tail,
-                uint32_t bw, int invert, int vec, hipStream_t stream) {
-    const int64_t chunks = ceil_div(g.wd, (int64_t)kWave);
-    const int64_t whole = vec ? std::min<int64_t>(chunks, g.width / (32 * kWave)) : 0;
-    const int rc = band.cache_policy == EDGE_CACHE_STREAM
-        ? launch_grey_band<MODE, StreamingStrip>(g, band, whole, bw, invert, stream)
-        : launch_grey_band<MODE, CachedStrip>(g, band, whole, bw, invert, stream);
-    if (rc) return rc;
-    return launch_grey_tail<MODE>(g, tail, whole, chunks - whole, bw, invert, stream);
+int launch_grey(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int invert, bool aligned,
+                hipStream_t stream) {
+    const bool nt = c.cache_policy == EDGE_CACHE_STREAM;
+    if (aligned) {
+        return nt ? launch_grey_band<MODE, true, StreamingStrip>(g, c, bw, invert, stream)
+                  : launch_grey_band<MODE, true, CachedStrip>(g, c, bw, invert, stream);
+    }
+    return nt ? launch_grey_band<MODE, false, StreamingStrip>(g, c, bw, invert, stream)
+              : launch_grey_band<MODE, false, CachedStrip>(g, c, bw, invert, stream);
 }
 
 template <int L, bool EDGEOUT>
@@ -1039,9 +1005,9 @@ int edge_threshold_pack(const void* grey, int64_t grey_stride_bytes, int thresho
     const int64_t threads = height * (int64_t)wd32;
     const int64_t blocks = ceil_div(threads, 256);
     if (!grid_fits(blocks, 256)) return EDGE_ERR_UNSUPPORTED;
-    const bool vec = (uintptr_t)grey % 16 == 0 && grey_stride_bytes % 16 == 0;
+    const bool aligned = (uintptr_t)grey % 16 == 0 && grey_stride_bytes % 16 == 0;
     hipStream_t s = (hipStream_t)hip_stream;
-    if (vec)
+    if (aligned)
         hipLaunchKernelGGL(k_pack<true>, dim3((uint32_t)blocks), dim3(256), 0, s,
                            (const uint8_t*)grey, grey_stride_bytes, (uint32_t*)out,
                            stride_words * per, (int32_t)height, (int32_t)width, wd32,
@@ -1089,32 +1055,28 @@ int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int thresh
     g.grey = (const uint8_t*)grey;
     g.grey_stride = grey_stride_bytes;
     g.thr = (uint32_t)threshold;
-    edge_launch_cfg band, tail;
+    edge_launch_cfg c;
     if (cfg) {
-        band = tail = *cfg;
+        c = *cfg;
     } else {
         // bands of 8 wavefronts x 2 rows (16 rows loaded, 14 out), cached:
         // measured 16.5 / 54.0 / 849 us at 8192^2 / 16384^2 / 65536^2,
         // within 1-2% of the best band shape at each and level with the
-        // threshold-and-pack pass alone; the byte-path strips: 4 wavefronts,
-        // strips of a height growing with the image
-        band.vec_words = tail.vec_words = 1;
-        band.blocks_per_cu = tail.blocks_per_cu = 1;
-        band.cache_policy = tail.cache_policy = EDGE_CACHE_NORMAL;
-        band.rows_per_tile = 2;
-        band.waves_per_block = 8;
-        const int64_t chunks = ceil_div(g.wd, (int64_t)kWave);
-        tail.rows_per_tile = (int32_t)pow2_floor(std::max<int64_t>(2, std::min<int64_t>(256, chunks * height / 2048)));
-        tail.waves_per_block = 4;
+        // threshold-and-pack pass alone
+        c.vec_words = 1;
+        c.blocks_per_cu = 1;
+        c.cache_policy = EDGE_CACHE_NORMAL;
+        c.rows_per_tile = 2;
+        c.waves_per_block = 8;
     }
-    const int vec = (uintptr_t)grey % 16 == 0 && grey_stride_bytes % 16 == 0;
+    const bool aligned = (uintptr_t)grey % 16 == 0 && grey_stride_bytes % 16 == 0;
     const uint32_t bw = border_word(border);
     const int inv = (flags & EDGE_FLAG_INVERT_OUT) ? 1 : 0;
     hipStream_t s = (hipStream_t)hip_stream;
     switch (kernel_mode(mode, flags)) {
-        case kModePlain: return launch_grey<kModePlain>(g, band, tail, bw, inv, vec, s);
-        case kModeFull: return launch_grey<kModeFull>(g, band, tail, bw, inv, vec, s);
-        default: return launch_grey<kModeClause2>(g, band, tail, bw, inv, vec, s);
+        case kModePlain: return launch_grey<kModePlain>(g, c, bw, inv, aligned, s);
+        case kModeFull: return launch_grey<kModeFull>(g, c, bw, inv, aligned, s);
+        default: return launch_grey<kModeClause2>(g, c, bw, inv, aligned, s);
     }
 }
 

@@ -111,6 +111,36 @@ def test_threshold_edges_fused(word_bits, H, W):
                 assert_same(unpack_rows(host, W), want, f"t={t} gs={gs} {border} {mode}")
 
 
+@pytest.mark.parametrize("W", [1, 31, 100, 2053, 4133])
+def test_grey_rows_at_every_alignment(W):
+    """Grey rows starting at every byte offset mod 16 (a base offset of
+    0..15 bytes and pitches of W + 0, 1, 3, 8 and 13 bytes), read from a
+    buffer that ends at the image's last byte: both threshold kernels equal
+    the oracle."""
+    import paper_1401_5245_amd as em
+    H = 19
+    grey = images.grey_image(H, W, seed=W)
+    want_pack = oracle.threshold(grey, 131)
+    want_edges = oracle.edge(want_pack, border="black")
+    S = row_words(W, 32)
+    packed = torch.zeros((H, S), dtype=torch.int32, device="cuda")
+    edges = torch.zeros((H, S), dtype=torch.int32, device="cuda")
+    for pad in (0, 1, 3, 8, 13):
+        gs = W + pad
+        for off in range(16):
+            flat = np.zeros(off + (H - 1) * gs + W, np.uint8)
+            for y in range(H):
+                flat[off + y * gs:off + y * gs + W] = grey[y]
+            buf = torch.from_numpy(flat).cuda()
+            view = buf[off:]
+            em.threshold_pack(view, packed, H, W, 131, grey_stride=gs)
+            em.threshold_edges(view, edges, H, W, 131, grey_stride=gs, border="black")
+            torch.cuda.synchronize()
+            tag = f"W={W} pitch={gs} offset={off}"
+            assert_same(unpack_rows(packed.cpu().numpy().view(np.uint32), W), want_pack, tag)
+            assert_same(unpack_rows(edges.cpu().numpy().view(np.uint32), W), want_edges, tag)
+
+
 def test_every_threshold_every_byte_value():
     """Every threshold 0..256 against a grey image that puts every byte
     value at every bit position of a 32-pixel word (value (x + 37y) mod 256
