@@ -131,13 +131,16 @@ __device__ __forceinline__ uint32_t threshold_word(const u32x4& a, const u32x4& 
 // (no load can fault, whatever the row's alignment or the word's place).
 // Bytes at or past the width come out as junk bits that the caller masks.
 // ALIGNED (r = 0): the word is two blocks; otherwise three, and the word's
-// bytes start r bytes into the first.
+// bytes start r bytes into the first. INSIDE: all 32 bytes of the word lie
+// in the row; aligned, both blocks then hold only row bytes and need no
+// clamp (unaligned, the third block of a row that happens to start on a
+// boundary holds none, so it stays clamped).
 template <bool ALIGNED>
 struct GreyBlocks {
     u32x4 q[ALIGNED ? 2 : 3];
 };
 
-template <bool ALIGNED, bool NT>
+template <bool ALIGNED, bool NT, bool INSIDE = false>
 __device__ __forceinline__ GreyBlocks<ALIGNED> load_grey_word(const uint8_t* row, int j,
                                                               int32_t width) {
     const uint32_t r = ALIGNED ? 0u : (uint32_t)((uintptr_t)row & 15u);
@@ -147,7 +150,7 @@ __device__ __forceinline__ GreyBlocks<ALIGNED> load_grey_word(const uint8_t* row
 #pragma unroll
     for (int b = 0; b < (ALIGNED ? 2 : 3); ++b) {
         uint32_t off = 32u * (uint32_t)j + 16u * b;
-        off = off < last ? off : last;
+        if constexpr (!(INSIDE && ALIGNED)) off = off < last ? off : last;
         const u32x4* p = reinterpret_cast<const u32x4*>(base + off);
         gb.q[b] = NT ? __builtin_nontemporal_load(p) : *p;
     }
@@ -483,13 +486,15 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
 // past the row end hold the border colour, pad bits too.
 constexpr int kBandPitch = kWave + 2;
 
-template <int MODE, int RW, bool ALIGNED, class Pol>
+// WHOLE: every pixel of the chunk lies inside the row (no clamps, no pad
+// bits); otherwise the row's last chunk.
+template <int MODE, int RW, bool ALIGNED, bool WHOLE, class Pol>
 __device__ __forceinline__ void grey_band_unit(const Geom& g, uint32_t* tile, int nw, int j0,
                                                int64_t y0, uint32_t bw, bool invert) {
     const int lane = threadIdx.x & (kWave - 1);
     const int w = wave_uniform(threadIdx.x / kWave);
     const int jl = j0 + lane;
-    const uint32_t vm = valid_bits(jl, g.width), om = bw & ~vm;
+    const uint32_t vm = WHOLE ? 0xffffffffu : valid_bits(jl, g.width), om = bw & ~vm;
     const int64_t xl = 32ll * j0 - 1, xr = 32ll * (j0 + kWave);
     const bool has_l = j0 > 0, has_r = xr < g.width;
     const bool edge_lane = lane == 0 || lane == kWave - 1;
@@ -502,7 +507,7 @@ __device__ __forceinline__ void grey_band_unit(const Geom& g, uint32_t* tile, in
         const int64_t y = y0 - 1 + i * nw + w;
         const int64_t yc = y < 0 ? 0 : (y >= g.height ? g.height - 1 : y);
         const uint8_t* rp = g.grey + yc * g.grey_stride;
-        q[i] = load_grey_word<ALIGNED, Pol::nt_load>(rp, jl, g.width);
+        q[i] = load_grey_word<ALIGNED, Pol::nt_load, WHOLE>(rp, jl, g.width);
         eb[i] = edge_lane ? rp[xe] : 0u;
     }
 #pragma unroll
@@ -513,7 +518,7 @@ __device__ __forceinline__ void grey_band_unit(const Geom& g, uint32_t* tile, in
         const bool inside = y >= 0 && y < g.height;
         uint32_t* t = tile + l * kBandPitch;
         const uint32_t word = grey_word<ALIGNED>(q[i], g.grey + yc * g.grey_stride, g.thr);
-        t[1 + lane] = inside ? ((word & vm) | om) : bw;
+        t[1 + lane] = inside ? (WHOLE ? word : ((word & vm) | om)) : bw;
         const uint32_t side = eb[i] >= g.thr ? 0xffffffffu : 0u;
         if (lane == 0) t[0] = inside && has_l ? side : bw;
         if (lane == kWave - 1) t[kBandPitch - 1] = inside && has_r ? side : bw;
@@ -537,7 +542,7 @@ __device__ __forceinline__ void grey_band_unit(const Geom& g, uint32_t* tile, in
         uint32_t dc, dw, de;
         row(o + 2, dc, dw, de);
         const int64_t y = y0 + o;
-        if (y < g.height && jl < g.wd) {
+        if (y < g.height && (WHOLE || jl < g.wd)) {
             const uint32_t v = edge_word<MODE>(cc, ue, uc, uw, cw, dw, dc, de, ce) & vm;
             uint32_t* op = g.out + y * g.stride + jl;
             const uint32_t res = invert ? (v ^ vm) : v;

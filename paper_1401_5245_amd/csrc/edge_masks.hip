@@ -48,8 +48,13 @@ __global__ void __launch_bounds__(512) k_grey_band(Geom g, int64_t chunks, int64
     for (int64_t unit = xcd_block(blockIdx.x, gridDim.x); unit < nunits; unit += gridDim.x) {
         const int64_t band = unit / chunks;
         const int64_t chunk = unit - band * chunks;
-        grey_band_unit<MODE, RW, ALIGNED, Pol>(g, band_tile, nw, (int)(chunk * kWave),
-                                               band * (nw * RW - 2), bw, invert != 0);
+        const int j0 = (int)(chunk * kWave);
+        if (32ll * (j0 + kWave) <= g.width)
+            grey_band_unit<MODE, RW, ALIGNED, true, Pol>(g, band_tile, nw, j0, band * (nw * RW - 2),
+                                                         bw, invert != 0);
+        else
+            grey_band_unit<MODE, RW, ALIGNED, false, Pol>(g, band_tile, nw, j0, band * (nw * RW - 2),
+                                                          bw, invert != 0);
         if (unit + gridDim.x < nunits) __syncthreads();
     }
 }

@@ -111,7 +111,7 @@ def test_threshold_edges_fused(word_bits, H, W):
                 assert_same(unpack_rows(host, W), want, f"t={t} gs={gs} {border} {mode}")
 
 
-@pytest.mark.parametrize("W", [1, 31, 100, 2053, 4133])
+@pytest.mark.parametrize("W", [1, 31, 100, 2048, 2053, 4096, 4133])
 def test_grey_rows_at_every_alignment(W):
     """Grey rows starting at every byte offset mod 16 (a base offset of
     0..15 bytes and pitches of W + 0, 1, 3, 8 and 13 bytes), read from a
