@@ -16,6 +16,7 @@ int oracle_edge_image(const uint8_t* img, uint8_t* out, int64_t H, int64_t W, in
                       int clauses, int invert);
 int oracle_peel(const uint8_t* img, uint8_t* out, int64_t H, int64_t W, int border_pixel,
                 int iterations, int edge_out);
+int oracle_threshold(const uint8_t* grey, uint8_t* out, int64_t H, int64_t W, int threshold);
 
 static uint64_t rng_state;
 
@@ -193,6 +194,58 @@ static int run_batch_case(int border, uint64_t seed) {
     return ok;
 }
 
+/* Grey input, thresholded and edge-detected in one call, from rows that
+ * start `offset` bytes past a 16-byte boundary with a pitch of W + pad
+ * bytes, the device buffer ending at the image's last byte. */
+static int run_grey_case(int64_t H, int64_t W, int64_t offset, int64_t pad, int threshold,
+                         uint64_t seed) {
+    const int64_t gs = W + pad, span = (H - 1) * gs + W;
+    const int64_t wd = (W + 31) / 32, n = H * wd;
+    uint8_t* grey = malloc((size_t)span);
+    uint8_t* dense = malloc((size_t)(H * W));
+    uint8_t* binary = malloc((size_t)(H * W));
+    uint8_t* want = malloc((size_t)(H * W));
+    uint32_t* back = malloc((size_t)n * 4);
+    uint8_t* dgrey = NULL;
+    void* dout = NULL;
+    int ok = 1, rc;
+    int64_t y, x;
+    rng_state = seed;
+    for (int64_t i = 0; i < span; ++i) grey[i] = (uint8_t)next_u64();
+    for (y = 0; y < H; ++y)
+        for (x = 0; x < W; ++x) dense[y * W + x] = grey[y * gs + x];
+    oracle_threshold(dense, binary, H, W, threshold);
+    oracle_edge_image(binary, want, H, W, 1, 1, 0);
+    HIP_OK(hipMalloc((void**)&dgrey, (size_t)(offset + span)));
+    HIP_OK(hipMalloc(&dout, (size_t)n * 4));
+    HIP_OK(hipMemcpy(dgrey + offset, grey, (size_t)span, hipMemcpyHostToDevice));
+    rc = edge_threshold_edges(dgrey + offset, gs, threshold, dout, H, W, wd, 32, EDGE_BORDER_WHITE,
+                              EDGE_MODE_MASKS, 0, NULL, NULL);
+    if (rc != EDGE_OK) {
+        printf("edge_threshold_edges: %s\n", edge_status_string(rc));
+        ok = 0;
+    } else {
+        HIP_OK(hipDeviceSynchronize());
+        HIP_OK(hipMemcpy(back, dout, (size_t)n * 4, hipMemcpyDeviceToHost));
+        for (y = 0; y < H && ok; ++y)
+            for (x = 0; x < W; ++x)
+                if ((uint8_t)((back[y * wd + x / 32] >> (x % 32)) & 1) != want[y * W + x]) {
+                    ok = 0;
+                    break;
+                }
+    }
+    HIP_OK(hipFree(dgrey));
+    HIP_OK(hipFree(dout));
+    free(grey);
+    free(dense);
+    free(binary);
+    free(want);
+    free(back);
+    printf("%s grey %lld x %lld offset %lld pitch %lld threshold %d\n", ok ? "match" : "MISMATCH",
+           (long long)H, (long long)W, (long long)offset, (long long)gs, threshold);
+    return ok;
+}
+
 int main(void) {
     static const int64_t shapes[][2] = {{1, 1}, {3, 33}, {5, 64}, {70, 1000}, {257, 2049},
                                         {33, 8193}};
@@ -211,6 +264,15 @@ int main(void) {
     for (int border = 0; border < 2; ++border) {
         all &= run_batch_case(border, 77u + (uint64_t)border);
         ++cases;
+    }
+    {
+        static const int64_t grey[][4] = {{1, 1, 0, 0}, {9, 100, 5, 3}, {17, 2048, 3, 0},
+                                          {15, 4133, 11, 13}, {30, 4096, 8, 8}};
+        for (size_t s = 0; s < sizeof(grey) / sizeof(grey[0]); ++s) {
+            all &= run_grey_case(grey[s][0], grey[s][1], grey[s][2], grey[s][3], 97 + 20 * (int)s,
+                                 500u + (uint64_t)s);
+            ++cases;
+        }
     }
     printf("%s: %d cases\n", all ? "all match" : "FAILED", cases);
     return all ? 0 : 1;

@@ -48,4 +48,4 @@ def test_c_program_matches_oracle():
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     print(r.stdout[-2000:])
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
-    assert "all match: 38 cases" in r.stdout
+    assert "all match: 43 cases" in r.stdout
