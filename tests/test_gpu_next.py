@@ -144,9 +144,8 @@ def test_grey_rows_at_every_alignment(W):
 def test_every_threshold_every_byte_value():
     """Every threshold 0..256 against a grey image that puts every byte
     value at every bit position of a 32-pixel word (value (x + 37y) mod 256
-    over 32 rows): the whole words take the 128-bit path of both kernels
-    (the first 2048 pixels of a row form a whole chunk of the fused kernel),
-    the last 256 pixels its byte path."""
+    over 32 rows), 2304 pixels wide: the fused kernel's first chunk lies
+    wholly inside the row, its second is the partial last chunk."""
     import paper_1401_5245_amd as em
     H, W = 32, 2304
     y, x = np.mgrid[0:H, 0:W]
@@ -168,9 +167,10 @@ def test_every_threshold_every_byte_value():
 @pytest.mark.parametrize("waves,rows", [(1, 1), (1, 8), (2, 2), (2, 4), (4, 4), (4, 8), (8, 2),
                                        (8, 8)])
 def test_threshold_edges_band_heights(waves, rows):
-    """Whole chunks run as bands of waves * rows' loaded rows (rows rounded
-    to 2, 4 or 8, at least four rows a band) less two: heights around one
-    and two bands, in every mode, with and without a byte-path tail."""
+    """The fused grey kernel runs bands of waves * rows' loaded rows (rows
+    rounded to 2, 4 or 8, at least four rows a band) less two: heights
+    around one and two bands, in every mode, with and without a partial
+    last chunk."""
     import paper_1401_5245_amd as em
     rw = 8 if rows >= 8 else (4 if rows >= 4 else 2)
     while waves * rw < 4:
