@@ -112,24 +112,28 @@ KERNEL_SOURCES = ("paper_1401_5245_amd/csrc/edge_device.hpp",
                   "paper_1401_5245_amd/csrc/edge_masks.hip")
 
 
-def measured_traffic(path: str = PROFILE):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, or
-    None when the kernel sources changed since the counters were taken."""
+def measured_traffic(path: str = PROFILE, index: int = 0):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary (its
+    index-th counter table, for profiles covering several kernels), or None
+    when the kernel sources changed since the counters were taken."""
     import hashlib
     try:
-        text = open(path).read()
+        text = open(os.path.join(ROOT, "profiles", path) if os.sep not in path else path).read()
     except OSError:
         return None
-    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line
-                  and line.split(": ", 1)[0] in ("traffic_bytes_per_launch",
-                                                 "kernel_source_sha256_16"))
+    fields = {"traffic_bytes_per_launch": [], "kernel_source_sha256_16": []}
+    for line in text.splitlines():
+        key, _, value = line.partition(": ")
+        if key in fields:
+            fields[key].append(value.strip())
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
+    if index >= len(fields["traffic_bytes_per_launch"]) or \
+            fields["kernel_source_sha256_16"][index] != h.hexdigest()[:16]:
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    return int(fields["traffic_bytes_per_launch"][index])
 
 
 def roofline(bytes_per_launch: float, ms: float, traffic=None) -> dict:
@@ -330,7 +334,8 @@ def plain_65536(torch, em, tm, steps):
     torch.cuda.empty_cache()
     return {"workload": "plain, 65536x65536 tiled glyph page (seed 22), uint64, 1 GiB per launch",
             "gpx_s": round(H * W / (ms * 1e-3) / 1e9, 1), "ms_per_launch": round(ms, 4),
-            "roofline": roofline(nbytes, ms), "sampled_rows_bit_exact": ok}
+            "roofline": roofline(nbytes, ms, measured_traffic("k_strip_plain_65536x65536_u64.md")),
+            "sampled_rows_bit_exact": ok}
 
 
 def next_rows_65536(torch, em, tm, steps=20):
@@ -366,7 +371,9 @@ def next_rows_65536(torch, em, tm, steps=20):
     nbytes = 5 * H * (W // 8)
     res["directions"] = {"workload": "65536x65536 tiled glyph page (seed 22), uint64: four "
                                      "fundamental-edge planes", "ms": round(ms, 4),
-                         "roofline": roofline(nbytes, ms), "sampled_rows_bit_exact": ok}
+                         "roofline": roofline(nbytes, ms,
+                                              measured_traffic("next_rows_65536x65536.md", 0)),
+                         "sampled_rows_bit_exact": ok}
     del inp, out4
     torch.cuda.empty_cache()
     log("building 65536x65536 grey image (8x8 tiles of the 8192^2 grey image, seed 7)")
@@ -386,7 +393,9 @@ def next_rows_65536(torch, em, tm, steps=20):
     res["threshold_edges"] = {"workload": "65536x65536 tiled grey image (seed 7), threshold 128, "
                                           "uint64 out", "ms": round(ms, 4),
                               "gpx_s": round(H * W / (ms * 1e-3) / 1e9, 1),
-                              "roofline": roofline(nbytes, ms), "sampled_rows_bit_exact": ok}
+                              "roofline": roofline(nbytes, ms,
+                                                   measured_traffic("next_rows_65536x65536.md", 1)),
+                              "sampled_rows_bit_exact": ok}
     del gt, out
     torch.cuda.empty_cache()
     return res
@@ -424,7 +433,8 @@ def full_16384(torch, em, tm, steps):
     return {"workload": "full definition, 16384x16384 skeleton+stroke page (seed 4), uint64, "
                         "10 rotating buffer pairs",
             "gpx_s": round(H * W / (ms * 1e-3) / 1e9, 1), "ms_per_launch": round(ms, 4),
-            "roofline": roofline(nbytes, ms), "sampled_rows_bit_exact": ok and ok2,
+            "roofline": roofline(nbytes, ms, measured_traffic("k_strip_full_16384x16384_u64.md")),
+            "sampled_rows_bit_exact": ok and ok2,
             "clause2_pixels_in_sample": n_c2}
 
 

@@ -38,5 +38,23 @@ def test_traffic_requires_matching_source_hash(tmp_path):
     assert bench.measured_traffic(str(tmp_path / "missing.md")) is None
 
 
+def test_traffic_takes_the_indexed_table(tmp_path):
+    import hashlib
+    import os
+    h = hashlib.sha256()
+    for f in bench.KERNEL_SOURCES:
+        with open(os.path.join(bench.ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    cur = h.hexdigest()[:16]
+    p = tmp_path / "two.md"
+    p.write_text(f"# two kernels\ntraffic_bytes_per_launch: 111\nkernel_source_sha256_16: {cur}\n"
+                 f"text: with a colon\ntraffic_bytes_per_launch: 222\n"
+                 f"kernel_source_sha256_16: 0123456789abcdef\n")
+    assert bench.measured_traffic(str(p)) == 111
+    assert bench.measured_traffic(str(p), 0) == 111
+    assert bench.measured_traffic(str(p), 1) is None        # taken with other sources
+    assert bench.measured_traffic(str(p), 2) is None        # no third table
+
+
 def test_host_cores_bounded():
     assert 1 <= bench.host_cores() <= 16
