@@ -670,6 +670,46 @@ def next_rows(torch, em, tm, steps):
     return res
 
 
+def peel_65536(torch, em, tm, steps=10):
+    """Iterated peeling at 65536^2 (1 GiB each way), where one pass of k
+    peels is bound by HBM rather than by the launch or the number of
+    wavefronts: k = 1, 2, 4 and 8, sampled rows checked against the oracle
+    run on full-width windows reaching k rows to either side (the k-th peel
+    of a pixel depends on nothing farther away)."""
+    from synth import images, pack_rows, unpack_rows
+    import oracle
+    H = W = 65536
+    log("building 65536x65536 page (8x8 tiles of an 8192^2 glyph page, seed 22)")
+    tile_img = images.glyph_page(8192, 8192, seed=22)
+    words = np.tile(pack_rows(tile_img, 64), (8, 8))
+    inp = words_tensor(torch, words)
+    del words
+    out = torch.empty_like(inp)
+    rows = (0, 1, 8191, 8192, 30000, 65534, 65535)
+    nbytes = 2 * H * (W // 64) * 8
+    runs = []
+    for k in (1, 2, 4, 8):
+        em.peel(inp, out, H, W, k)
+        torch.cuda.synchronize()
+        ok = True
+        for r in rows:
+            lo, hi = max(0, r - k), min(H, r + k + 1)
+            win = np.tile(np.stack([tile_img[y % 8192] for y in range(lo, hi)]), (1, 8))
+            got = unpack_rows(out[r:r + 1].cpu().numpy().view(np.uint64), W)[0]
+            ok &= bool(np.array_equal(got, oracle.peel(win, k)[r - lo]))
+        for _ in range(3):
+            em.peel(inp, out, H, W, k)
+        ms = tm.per_call_ms(lambda i: em.peel(inp, out, H, W, k), steps)
+        runs.append({"k": k, "ms": round(ms, 4),
+                     "gpx_peels_s": round(H * W * k / (ms * 1e-3) / 1e9, 1),
+                     "roofline": roofline(nbytes, ms), "sampled_rows_bit_exact": ok})
+    del inp, out
+    torch.cuda.empty_cache()
+    return {"workload": "iterated peeling of the 65536x65536 tiled glyph page (seed 22), uint64, "
+                        "white border; one edge_peel call of k peels, 1 GiB each way",
+            "runs": runs}
+
+
 def peel_section(torch, em, tm, ks=(1, 2, 4, 8, 16, 30)):
     """Iterated peeling of the 8192^2 glyph page (uint64): k peels in one
     fused pass against k launches of a single peel (ping-pong buffers);
@@ -953,6 +993,7 @@ SECTIONS = {
     "size_sweep": lambda torch, em, tm, a: size_sweep(torch, em, tm),
     "content": lambda torch, em, tm, a: content_independence(torch, em, tm),
     "peel": lambda torch, em, tm, a: peel_section(torch, em, tm),
+    "peel_65536": lambda torch, em, tm, a: peel_65536(torch, em, tm),
     "serving": lambda torch, em, tm, a: serving(torch, em),
     "cpu_configs": lambda torch, em, tm, a: cpu_oracle_configs(None),
     # the plain copy of 8 MiB or 512 MiB: the reference reading that scales
