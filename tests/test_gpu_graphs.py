@@ -19,7 +19,12 @@ def test_captured_launches_replay_exactly():
     grey = images.grey_image(H, W, seed=13)
     inp = to_device_words(pack_rows(img, 64))
     gt = torch.from_numpy(grey).cuda()
-    outs = {k: torch.empty_like(inp) for k in ("masks", "full", "thr", "peel", "layer")}
+    flat = np.zeros(5 + (H - 1) * (W + 3) + W, np.uint8)    # rows off 16-byte boundaries
+    for y in range(H):
+        flat[5 + y * (W + 3):5 + y * (W + 3) + W] = grey[y]
+    gu = torch.from_numpy(flat).cuda()[5:]
+    outs = {k: torch.empty_like(inp)
+            for k in ("masks", "full", "thr", "thr_unaligned", "pack", "peel", "layer")}
     planes = torch.empty((4,) + tuple(inp.shape), dtype=inp.dtype, device="cuda")
 
     def launches():
@@ -27,6 +32,8 @@ def test_captured_launches_replay_exactly():
         em.edge_full(inp, outs["full"], H, W)
         em.edge_directions(inp, planes, H, W)
         em.threshold_edges(gt, outs["thr"], H, W, 128)
+        em.threshold_edges(gu, outs["thr_unaligned"], H, W, 128, grey_stride=W + 3)
+        em.threshold_pack(gu, outs["pack"], H, W, 128, grey_stride=W + 3)
         em.peel(inp, outs["peel"], H, W, 6)
         em.peel(inp, outs["layer"], H, W, 6, edge_out=True)
 
@@ -57,4 +64,5 @@ def test_captured_launches_replay_exactly():
             assert torch.equal(v, ref[k]), f"replay {rep}: {k}"
         assert torch.equal(planes, ref_planes), f"replay {rep}: planes"
         assert torch.equal(scratch, ref["masks"])
+    assert torch.equal(ref["thr"], ref["thr_unaligned"])
     del g
