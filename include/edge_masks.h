@@ -215,8 +215,10 @@ int edge_masks_staged(const void* in, void* out, void* scratch, int64_t scratch_
  * 0 <= iterations <= EDGE_PEEL_MAX_ITERATIONS, all done in one pass over
  * the image. cfg: NULL, or a configuration. With two or more levels
  * (iterations, plus one with EDGE_FLAG_PEEL_EDGE) its rows_per_tile and
- * waves_per_block are used, and with two or three levels also vec_words
- * (words per lane, narrowed as the pointers and stride require); loads
+ * waves_per_block are used, and with two to seven levels also vec_words
+ * (words per lane, narrowed as the pointers and stride require; the
+ * built-in shape takes four words per lane for two or three levels, and for
+ * four to seven on images of 2^30 pixels or more); loads
  * always go through the caches, and from 16 levels each strip takes one
  * workgroup of two wavefronts. One level or none runs the strip loop of
  * edge_image_launch, which reads every field as that call does. */

@@ -723,9 +723,13 @@ __device__ __forceinline__ void peel_unit(const Geom& g, int64_t chunk, int y0, 
 // Per level and row: the words' funnel shifts and ORs as in peel_unit, the
 // DPP carries once per lane, the halo word's own level. Warm-up as in
 // peel_unit. WHOLE: the span lies inside the row (vector loads and stores).
-// Used up to three levels, where its lane work per word is lowest against
-// the memory work and every instantiation is checked against the oracle.
-constexpr int kPeelVecLevels = 3;
+// Built for up to seven levels. Its loop body ends in a scheduling barrier
+// only up to three levels: with the barrier and the warm-up switch-on
+// together, the four-level instantiation came out of -O3 giving wrong
+// words (exact at -O1, or with either taken out), and from four levels on
+// the barrier does not pay anyway.
+constexpr int kPeelVecLevels = 7;
+constexpr int kPeelVecBarrierLevels = 3;
 
 template <int L, bool EDGEOUT, int VW, bool WHOLE, class Pol>
 __device__ __forceinline__ void peel_vec_unit(const Geom& g, int j0, int y0, int y1,
@@ -839,7 +843,7 @@ __device__ __forceinline__ void peel_vec_unit(const Geom& g, int j0, int y0, int
             const Raw w = q[u];
             q[u] = load(min(t + u + P, tlast));
             step(act_tag, t + u, w);
-            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (L <= kPeelVecBarrierLevels) __builtin_amdgcn_sched_barrier(0);
         }
     };
     constexpr auto all = std::integral_constant<int, L>{};

@@ -908,9 +908,17 @@ int launch_peel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int levels
 // wavefronts); 4 wavefronts per workgroup. cache_policy is not used: peel
 // units load through the caches, which keep the halo rows that
 // neighbouring strips share.
-edge_launch_cfg default_peel(int64_t height, int64_t wd32, int levels) {
+// Two or three levels: four words per lane at any size. Four to seven
+// levels on images of 2^30 pixels and more: four words per lane in 32-row
+// strips (measured, against the one-word unit in its built-in strips:
+// 32768^2 4 / 7 peels about 49 / 66 against 53 / 73 us, 65536^2 216 / 277
+// against 238-264 / 295-298 us; at 16384^2 level, at 8192^2 slower), when
+// the image's alignment allows it (vec_ok), else the one-word shape.
+edge_launch_cfg default_peel(int64_t height, int64_t wd32, int levels, bool vec_ok = true) {
     edge_launch_cfg c;
-    c.vec_words = levels <= kPeelVecLevels ? 4 : 1;
+    const bool large = vec_ok && levels >= 4 && levels <= kPeelVecLevels &&
+                       height * wd32 * 32 >= (int64_t(1) << 30);
+    c.vec_words = (vec_ok && levels <= 3) || large ? 4 : 1;
     c.blocks_per_cu = 1;
     c.cache_policy = EDGE_CACHE_NORMAL;
     c.waves_per_block = 4;
@@ -919,6 +927,7 @@ edge_launch_cfg default_peel(int64_t height, int64_t wd32, int levels) {
     while (rows <= levels && rows < 64) rows *= 2;
     const int64_t many = levels >= kPeelSplitLevels ? 4096 : 8192;
     if (rows < 64 && chunks * ceil_div(height, rows) > many) rows *= 2;
+    if (large) rows = 32;
     // keep the grid (one or two wavefronts per strip) within 2^32 work-items
     const int64_t max_units = levels >= kPeelSplitLevels ? (1ll << 25) : (1ll << 26);
     while (chunks * ceil_div(height, rows) >= max_units && rows < 1024) rows *= 2;
@@ -1131,9 +1140,11 @@ int edge_peel(const void* in, void* out, int64_t height, int64_t width, int64_t 
         if (edge_out) return launch_single<kModePlain>(g, vw, c, bw, 0, s);
         return launch_single<kModePeel>(g, vw, c, bw, 0, s);
     }
-    const edge_launch_cfg c = cfg ? *cfg : default_peel(height, g.wd, levels);
+    edge_launch_cfg c = cfg ? *cfg : default_peel(height, g.wd, levels);
     const int vmax = std::min(c.vec_words, std::min(alignment_words(pin), alignment_words(pout)));
     const int vw = pick_vw(g.wd, vmax, 0, g.stride);
+    // the built-in shape for four words per lane, but the image allows one
+    if (!cfg && vw < 2 && levels >= 4) c = default_peel(height, g.wd, levels, false);
     if (edge_out) return launch_peel<2, true>(g, c, bw, levels, vw, s);
     return launch_peel<2, false>(g, c, bw, levels, vw, s);
 }

@@ -1,5 +1,7 @@
 """Iterated edge peeling on the GPU (edge_peel), bit-exact against the
 oracle's repeated peel, plus properties that hold at any size."""
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -110,6 +112,43 @@ def test_peel_8192_sampled_rows(k):
         torch.cuda.synchronize()
         got = unpack_rows(out[rows].cpu().numpy().view(np.uint64), W)
         assert_same(got, oracle_rows(img, k, rows, edge_out=edge_out), f"k={k} {edge_out}")
+
+
+@functools.lru_cache(maxsize=1)
+def _page_32768():
+    """The 8192^2 glyph page of seed 5 tiled 4 x 4, and its uint64 words."""
+    img = np.tile(images.glyph_page(8192, 8192, seed=5), (4, 4))
+    return img, pack_rows(img, 64)
+
+
+@pytest.mark.parametrize("k", [4, 5, 6, 7])
+def test_peel_32768_sampled_rows(k):
+    """A 32768^2 image (2^30 pixels: four to seven levels take four words
+    per lane in the built-in shape), uint64 words, and the same image in
+    uint32 words from a start that is 4 bytes off an 8-byte boundary (one
+    word per lane, the one-word shape): sampled rows against the oracle on
+    row windows."""
+    import paper_1401_5245_amd as em
+    H = W = 32768
+    log(f"peel 32768^2 k={k}")
+    img, words = _page_32768()
+    rows = [0, 1, 2, 31, 32, 33, 16383, 16384, 32735, 32766, 32767]
+    inp = to_device_words(words)
+    out = torch.empty_like(inp)
+    w32 = words.view(np.uint32)
+    flat = torch.zeros(w32.size + 1, dtype=torch.int32, device="cuda")
+    flat[1:] = torch.from_numpy(w32.reshape(-1).view(np.int32)).cuda()
+    inp_odd = flat[1:].view(H, -1)                         # 4 bytes past an 8-byte boundary
+    out_odd = torch.empty_like(inp_odd)
+    for edge_out in (False, True):
+        want = oracle_rows(img, k, rows, edge_out=edge_out)
+        em.peel(inp, out, H, W, k, edge_out=edge_out)
+        em.peel(inp_odd, out_odd, H, W, k, edge_out=edge_out)
+        torch.cuda.synchronize()
+        got = unpack_rows(out[rows].cpu().numpy().view(np.uint64), W)
+        assert_same(got, want, f"k={k} {edge_out} uint64")
+        got = unpack_rows(out_odd[rows].cpu().numpy().view(np.uint32), W)
+        assert_same(got, want, f"k={k} {edge_out} uint32, odd start")
 
 
 def test_peel_composes():
