@@ -63,10 +63,8 @@ def parse():
 
 
 def ensure_built():
-    from paper_1401_5245_amd import build as hip_build
-    if not os.path.exists(hip_build.LIB):
-        import __graft_entry__
-        __graft_entry__.build()
+    import __graft_entry__
+    __graft_entry__.ensure_built()
 
 
 class Timer:

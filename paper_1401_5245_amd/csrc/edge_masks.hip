@@ -12,10 +12,10 @@
 #include <stdint.h>
 #include <string.h>
 
-#include "edge_device.hpp"
-#include "edge_masks.h"
+#include "edge_host.hpp"
 
 using namespace edgek;
+using namespace edgeh;
 
 static_assert(kMaxHeight == EDGE_MAX_HEIGHT, "one height limit for the header and the kernels");
 
@@ -34,81 +34,6 @@ __global__ void __launch_bounds__(512) k_strip(Geom g, int64_t chunks, int rows,
     const int64_t y0 = strip * rows;
     const int64_t y1 = y0 + rows < g.height ? y0 + rows : g.height;
     strip_unit<VW, MODE, Pol>(g, (int)(chunk * kWave * VW), (int)y0, (int)y1, bw, invert != 0);
-}
-
-// Grey image in, edge map out: units are bands of nw * RW - 2 output rows
-// of one 64-word chunk, one per workgroup; a grid smaller than the unit
-// count (very tall images) takes them in turns, the LDS tile reused after
-// a barrier.
-template <int MODE, int RW, bool ALIGNED, class Pol>
-__global__ void __launch_bounds__(512) k_grey_band(Geom g, int64_t chunks, int64_t nunits,
-                                                   uint32_t bw, int invert) {
-    extern __shared__ uint32_t band_tile[];
-    const int nw = blockDim.x / kWave;
-    for (int64_t unit = xcd_block(blockIdx.x, gridDim.x); unit < nunits; unit += gridDim.x) {
-        const int64_t band = unit / chunks;
-        const int64_t chunk = unit - band * chunks;
-        const int j0 = (int)(chunk * kWave);
-        if (32ll * (j0 + kWave) <= g.width)
-            grey_band_unit<MODE, RW, ALIGNED, true, Pol>(g, band_tile, nw, j0, band * (nw * RW - 2),
-                                                         bw, invert != 0);
-        else
-            grey_band_unit<MODE, RW, ALIGNED, false, Pol>(g, band_tile, nw, j0, band * (nw * RW - 2),
-                                                          bw, invert != 0);
-        if (unit + gridDim.x < nunits) __syncthreads();
-    }
-}
-
-// Iterated peeling of one image: strips of `rows` rows x kPeelSpan words,
-// one wavefront per strip, L levels.
-template <int L, bool EDGEOUT, class Pol>
-__global__ void __launch_bounds__(512) k_peel(Geom g, int64_t chunks, int rows, int64_t nunits,
-                                              uint32_t bw) {
-    const int wpb = blockDim.x / kWave;
-    const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
-                         wave_uniform(threadIdx.x / kWave);
-    if (unit >= nunits) return;
-    const int64_t strip = unit / chunks;
-    const int64_t chunk = unit - strip * chunks;
-    const int64_t y0 = strip * rows;
-    const int64_t y1 = y0 + rows < g.height ? y0 + rows : g.height;
-    peel_unit<L, EDGEOUT, Pol>(g, chunk, (int)y0, (int)y1, bw);
-}
-
-// Iterated peeling with VW words per lane: strips of `rows` rows x 64*VW
-// words, one wavefront per strip, L levels.
-template <int L, bool EDGEOUT, int VW>
-__global__ void __launch_bounds__(512) k_peel_vec(Geom g, int64_t chunks, int rows,
-                                                  int64_t nunits, uint32_t bw) {
-    const int wpb = blockDim.x / kWave;
-    const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
-                         wave_uniform(threadIdx.x / kWave);
-    if (unit >= nunits) return;
-    const int64_t strip = unit / chunks;
-    const int64_t chunk = unit - strip * chunks;
-    const int64_t y0 = strip * rows;
-    const int64_t y1 = y0 + rows < g.height ? y0 + rows : g.height;
-    const int j0 = (int)(chunk * kWave * VW);
-    if (j0 + kWave * VW <= g.wd)
-        peel_vec_unit<L, EDGEOUT, VW, true, CachedStrip>(g, j0, (int)y0, (int)y1, bw);
-    else
-        peel_vec_unit<L, EDGEOUT, VW, false, CachedStrip>(g, j0, (int)y0, (int)y1, bw);
-}
-
-// Iterated peeling with a strip's levels split over the two wavefronts of
-// a workgroup (one strip per workgroup, so both leave together).
-template <int LA, int LB, bool EDGEOUT>
-__global__ void __launch_bounds__(2 * kWave) k_peel_split(Geom g, int64_t chunks, int rows,
-                                                         int64_t nunits, uint32_t bw) {
-    __shared__ uint32_t xfer[2 * kPeelSplitGroup][kWave];
-    const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x);
-    if (unit >= nunits) return;
-    const int role = wave_uniform(threadIdx.x / kWave);
-    const int64_t strip = unit / chunks;
-    const int64_t chunk = unit - strip * chunks;
-    const int64_t y0 = strip * rows;
-    const int64_t y1 = y0 + rows < g.height ? y0 + rows : g.height;
-    peel_split_unit<LA, LB, EDGEOUT, CachedStrip>(g, chunk, (int)y0, (int)y1, bw, role, xfer);
 }
 
 // One image with rows of <= 32 words, `band` rows per wavefront.
@@ -370,24 +295,6 @@ __global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out
     }
 }
 
-// Threshold binarisation + packing (section 7: a grey image is first made
-// binary by a threshold): one 32-bit output word per thread, from the 16-byte
-// blocks that hold its 32 grey bytes; a byte >= thr becomes white (1). Rows
-// of `gstride` bytes in, packed rows of `stride` 32-bit words out; bits past
-// the width are 0. ALIGNED: the grey pointer and pitch are 16-byte aligned.
-template <bool ALIGNED>
-__global__ void __launch_bounds__(256) k_pack(const uint8_t* grey, int64_t gstride, uint32_t* out,
-                                              int64_t stride, int32_t height, int32_t width,
-                                              int32_t wd, uint32_t thr) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)height * wd) return;
-    const int64_t y = t / wd;
-    const int j = (int)(t - y * wd);
-    const uint8_t* rp = grey + y * gstride;
-    const GreyBlocks<ALIGNED> q = load_grey_word<ALIGNED, false>(rp, j, width);
-    out[y * stride + j] = grey_word<ALIGNED>(q, rp, thr) & valid_bits(j, width);
-}
-
 // The paper's method as separate whole-image passes (sections 3-5), each a
 // block operation over 32-bit words, one word per thread. Used as the
 // unfused ablation of the fused kernels. Pixels past the width read as the
@@ -453,87 +360,7 @@ __global__ void __launch_bounds__(256) k_copy(const u32x4* in, u32x4* out, int64
 
 namespace {
 
-thread_local int g_last_hip = 0;
-
-int hip_failed(hipError_t e) {
-    g_last_hip = (int)e;
-    return EDGE_ERR_HIP;
-}
-
-int launch_status() {
-    const hipError_t e = hipGetLastError();
-    return e == hipSuccess ? EDGE_OK : hip_failed(e);
-}
-
-constexpr int kMaxDevices = 64;
-std::atomic<int> g_cu_count[kMaxDevices];
-
-int cu_count(int* out) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_failed(e);
-    if (dev >= 0 && dev < kMaxDevices) {
-        const int c = g_cu_count[dev].load(std::memory_order_relaxed);
-        if (c > 0) { *out = c; return EDGE_OK; }
-    }
-    int n = 0;
-    e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return hip_failed(e);
-    if (n <= 0) n = 1;
-    if (dev >= 0 && dev < kMaxDevices) g_cu_count[dev].store(n, std::memory_order_relaxed);
-    *out = n;
-    return EDGE_OK;
-}
-
-bool cfg_ok(const edge_launch_cfg& c) {
-    return (c.vec_words == 1 || c.vec_words == 2 || c.vec_words == 4) && c.rows_per_tile >= 1 &&
-           c.rows_per_tile <= 1024 &&
-           (c.waves_per_block == 1 || c.waves_per_block == 2 || c.waves_per_block == 4 ||
-            c.waves_per_block == 8) &&
-           c.blocks_per_cu >= 1 && c.blocks_per_cu <= 32 && c.cache_policy >= EDGE_CACHE_AUTO &&
-           c.cache_policy <= EDGE_CACHE_STREAM;
-}
-
-int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-// A dispatch carries its grid size in work-items as a 32-bit number.
-bool grid_fits(int64_t blocks, int64_t threads_per_block) {
-    return blocks >= 0 && blocks * threads_per_block <= (int64_t)UINT32_MAX;
-}
-
-int64_t pow2_floor(int64_t v) {
-    int64_t p = 1;
-    while (p * 2 <= v) p *= 2;
-    return p;
-}
-
-int common_checks(int word_bits, int border, int mode, uint32_t flags, bool batch = false) {
-    if (word_bits != 32 && word_bits != 64) return EDGE_ERR_INVALID;
-    if (border != EDGE_BORDER_WHITE && border != EDGE_BORDER_BLACK) return EDGE_ERR_INVALID;
-    if (mode != EDGE_MODE_MASKS && mode != EDGE_MODE_FULL) return EDGE_ERR_INVALID;
-    const uint32_t known = EDGE_FLAG_CLAUSE2_ONLY | EDGE_FLAG_INVERT_OUT |
-                           (batch ? (uint32_t)EDGE_FLAG_PLANNED : 0u);
-    if (flags & ~known) return EDGE_ERR_INVALID;
-    if ((flags & EDGE_FLAG_CLAUSE2_ONLY) && mode != EDGE_MODE_FULL) return EDGE_ERR_INVALID;
-    return EDGE_OK;
-}
-
-int kernel_mode(int mode, uint32_t flags) {
-    if (mode == EDGE_MODE_MASKS) return kModePlain;
-    return (flags & EDGE_FLAG_CLAUSE2_ONLY) ? kModeClause2 : kModeFull;
-}
-
-uint32_t border_word(int border) { return border == EDGE_BORDER_WHITE ? 0xffffffffu : 0u; }
-
-bool ranges_overlap(uintptr_t a, uint64_t na, uintptr_t b, uint64_t nb) {
-    return a < b + nb && b < a + na;
-}
-
-int alignment_words(uintptr_t p) {
-    if (p % 16 == 0) return 4;
-    if (p % 8 == 0) return 2;
-    return 1;
-}
+using namespace edgeh;
 
 // Built-in single-image shape, from the tuned shapes of square images of
 // 2048^2 .. 65536^2 on gfx950. Rows of <= 32 words: narrow units of up to 16
@@ -790,116 +617,6 @@ struct EdgeGraph {
     hipGraphExec_t exec;
 };
 
-// Workgroups of one grey-band launch at most (2^22 x 512 threads stays
-// below the grid's 2^32 threads); beyond, each takes several bands.
-constexpr int64_t kMaxBandBlocks = int64_t(1) << 22;
-
-template <int MODE, int RW, bool ALIGNED, class Pol>
-int launch_grey_band_rw(const Geom& g, int nw, int64_t chunks, uint32_t bw, int invert,
-                        hipStream_t stream) {
-    const int64_t nunits = chunks * ceil_div(g.height, (int64_t)(nw * RW - 2));
-    const int64_t blocks = std::min<int64_t>(nunits, kMaxBandBlocks);
-    const size_t lds = (size_t)nw * RW * kBandPitch * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_grey_band<MODE, RW, ALIGNED, Pol>), dim3((uint32_t)blocks),
-                       dim3(nw * kWave), lds, stream, g, chunks, nunits, bw, invert);
-    return launch_status();
-}
-
-// Band shape from the launch shape: waves_per_block wavefronts, each
-// loading rows_per_tile rows rounded down to 2, 4 or 8 (a band loads at
-// least four rows).
-template <int MODE, bool ALIGNED, class Pol>
-int launch_grey_band(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int invert,
-                     hipStream_t stream) {
-    const int64_t chunks = ceil_div(g.wd, (int64_t)kWave);
-    const int nw = c.waves_per_block;
-    int rw = c.rows_per_tile >= 8 ? 8 : (c.rows_per_tile >= 4 ? 4 : 2);
-    while (nw * rw < 4) rw *= 2;
-    if (rw == 8) return launch_grey_band_rw<MODE, 8, ALIGNED, Pol>(g, nw, chunks, bw, invert, stream);
-    if (rw == 4) return launch_grey_band_rw<MODE, 4, ALIGNED, Pol>(g, nw, chunks, bw, invert, stream);
-    return launch_grey_band_rw<MODE, 2, ALIGNED, Pol>(g, nw, chunks, bw, invert, stream);
-}
-
-// Rows that start on 16-byte boundaries (pointer and pitch) load two
-// blocks per word, others three. Streaming (non-temporal) loads and stores
-// only when asked for: bands re-read their first and last rows from the
-// cache, and cached was faster at every size measured (8192^2 to 65536^2).
-template <int MODE>
-int launch_grey(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int invert, bool aligned,
-                hipStream_t stream) {
-    const bool nt = c.cache_policy == EDGE_CACHE_STREAM;
-    if (aligned) {
-        return nt ? launch_grey_band<MODE, true, StreamingStrip>(g, c, bw, invert, stream)
-                  : launch_grey_band<MODE, true, CachedStrip>(g, c, bw, invert, stream);
-    }
-    return nt ? launch_grey_band<MODE, false, StreamingStrip>(g, c, bw, invert, stream)
-              : launch_grey_band<MODE, false, CachedStrip>(g, c, bw, invert, stream);
-}
-
-template <int L, bool EDGEOUT>
-int launch_peel_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, hipStream_t s) {
-    const int64_t chunks = ceil_div(g.wd, (int64_t)kPeelSpan);
-    const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
-    const int64_t blocks = ceil_div(nunits, c.waves_per_block);
-    if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL((k_peel<L, EDGEOUT, CachedStrip>), dim3((uint32_t)blocks),
-                       dim3(c.waves_per_block * kWave), 0, s, g, chunks, c.rows_per_tile, nunits,
-                       bw);
-    return launch_status();
-}
-
-template <int L, bool EDGEOUT, int VW>
-int launch_peel_vec_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, hipStream_t s) {
-    const int64_t chunks = ceil_div(g.wd, (int64_t)kWave * VW);
-    const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
-    const int64_t blocks = ceil_div(nunits, c.waves_per_block);
-    if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL((k_peel_vec<L, EDGEOUT, VW>), dim3((uint32_t)blocks),
-                       dim3(c.waves_per_block * kWave), 0, s, g, chunks, c.rows_per_tile, nunits,
-                       bw);
-    return launch_status();
-}
-
-// From this many levels a strip's levels are split over two wavefronts.
-constexpr int kPeelSplitLevels = 16;
-
-template <int L, bool EDGEOUT>
-int launch_peel_split_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t bw,
-                             hipStream_t s) {
-    const int64_t chunks = ceil_div(g.wd, (int64_t)kPeelSpan);
-    const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
-    if (!grid_fits(nunits, 2 * kWave)) return EDGE_ERR_UNSUPPORTED;
-    constexpr int LA = peel_split_first(L);
-    hipLaunchKernelGGL((k_peel_split<LA, L - LA, EDGEOUT>), dim3((uint32_t)nunits),
-                       dim3(2 * kWave), 0, s, g, chunks, c.rows_per_tile, nunits, bw);
-    return launch_status();
-}
-
-// One instantiation per level count 2..31 (levels are a template constant
-// so that every level's rows stay in registers).
-// vw: words per lane that the image's alignment allows (2 or 4 select the
-// vector-width unit up to kPeelVecLevels levels).
-template <int L, bool EDGEOUT>
-int launch_peel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int levels, int vw,
-                hipStream_t s) {
-    if constexpr (L > 31) {
-        return EDGE_ERR_INVALID;
-    } else {
-        if (levels == L) {
-            if constexpr (L >= kPeelSplitLevels) {
-                return launch_peel_split_kernel<L, EDGEOUT>(g, c, bw, s);
-            } else if constexpr (L <= kPeelVecLevels) {
-                if (vw == 4) return launch_peel_vec_kernel<L, EDGEOUT, 4>(g, c, bw, s);
-                if (vw == 2) return launch_peel_vec_kernel<L, EDGEOUT, 2>(g, c, bw, s);
-                return launch_peel_kernel<L, EDGEOUT>(g, c, bw, s);
-            } else {
-                return launch_peel_kernel<L, EDGEOUT>(g, c, bw, s);
-            }
-        }
-        return launch_peel<L + 1, EDGEOUT>(g, c, bw, levels, vw, s);
-    }
-}
-
 // Built-in peel shape, from sweeps at 8192^2 and 16384^2: a unit walks
 // 2 * levels halo rows besides its strip (the first half of them with few
 // levels formed), so strips are the smallest power of two above the level
@@ -934,6 +651,19 @@ edge_launch_cfg default_peel(int64_t height, int64_t wd32, int levels, bool vec_
     c.rows_per_tile = (int32_t)rows;
     return c;
 }
+
+}  // namespace
+
+int edgeh::peel_launch(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int levels, int vw,
+                       bool edge_out, hipStream_t s) {
+    if (levels >= 2 && levels <= 7) return peel_launch_2_7(g, c, bw, levels, vw, edge_out, s);
+    if (levels >= 8 && levels <= 15) return peel_launch_8_15(g, c, bw, levels, vw, edge_out, s);
+    if (levels >= 16 && levels <= 23) return peel_launch_16_23(g, c, bw, levels, vw, edge_out, s);
+    if (levels >= 24 && levels <= 31) return peel_launch_24_31(g, c, bw, levels, vw, edge_out, s);
+    return EDGE_ERR_INVALID;
+}
+
+namespace {
 
 template <int STAGE>
 int launch_stage(const uint32_t* img, const uint32_t* src, uint32_t* dst, int64_t stride,
@@ -1021,17 +751,9 @@ int edge_threshold_pack(const void* grey, int64_t grey_stride_bytes, int thresho
     if (!grid_fits(blocks, 256)) return EDGE_ERR_UNSUPPORTED;
     const bool aligned = (uintptr_t)grey % 16 == 0 && grey_stride_bytes % 16 == 0;
     hipStream_t s = (hipStream_t)hip_stream;
-    if (aligned)
-        hipLaunchKernelGGL(k_pack<true>, dim3((uint32_t)blocks), dim3(256), 0, s,
-                           (const uint8_t*)grey, grey_stride_bytes, (uint32_t*)out,
-                           stride_words * per, (int32_t)height, (int32_t)width, wd32,
-                           (uint32_t)threshold);
-    else
-        hipLaunchKernelGGL(k_pack<false>, dim3((uint32_t)blocks), dim3(256), 0, s,
-                           (const uint8_t*)grey, grey_stride_bytes, (uint32_t*)out,
-                           stride_words * per, (int32_t)height, (int32_t)width, wd32,
-                           (uint32_t)threshold);
-    return launch_status();
+    return pack_launch((const uint8_t*)grey, grey_stride_bytes, (uint32_t*)out, stride_words * per,
+                       (int32_t)height, (int32_t)width, wd32, (uint32_t)threshold, aligned, blocks,
+                       s);
 }
 
 int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int threshold, void* out,
@@ -1087,11 +809,7 @@ int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int thresh
     const uint32_t bw = border_word(border);
     const int inv = (flags & EDGE_FLAG_INVERT_OUT) ? 1 : 0;
     hipStream_t s = (hipStream_t)hip_stream;
-    switch (kernel_mode(mode, flags)) {
-        case kModePlain: return launch_grey<kModePlain>(g, c, bw, inv, aligned, s);
-        case kModeFull: return launch_grey<kModeFull>(g, c, bw, inv, aligned, s);
-        default: return launch_grey<kModeClause2>(g, c, bw, inv, aligned, s);
-    }
+    return grey_edges_launch(g, c, bw, inv, aligned, kernel_mode(mode, flags), s);
 }
 
 int edge_peel(const void* in, void* out, int64_t height, int64_t width, int64_t stride_words,
@@ -1145,8 +863,7 @@ int edge_peel(const void* in, void* out, int64_t height, int64_t width, int64_t 
     const int vw = pick_vw(g.wd, vmax, 0, g.stride);
     // the built-in shape for four words per lane, but the image allows one
     if (!cfg && vw < 2 && levels >= 4) c = default_peel(height, g.wd, levels, false);
-    if (edge_out) return launch_peel<2, true>(g, c, bw, levels, vw, s);
-    return launch_peel<2, false>(g, c, bw, levels, vw, s);
+    return peel_launch(g, c, bw, levels, vw, edge_out, s);
 }
 
 int edge_masks_staged(const void* in, void* out, void* scratch, int64_t scratch_bytes,
