@@ -43,6 +43,8 @@
  * CALLING RULES
  *   - All device pointers are caller-owned device memory. The library
  *     allocates no device memory; graph handles are the only objects it owns.
+ *     (edge_batch_noalloc's workspace is a fixed array inside the library's
+ *     code object, one per GPU, that exists once the library is loaded.)
  *   - Every call is asynchronous on `hip_stream` (a hipStream_t; NULL = the
  *     null stream) and returns once the work is enqueued. Inputs must stay
  *     valid and unmodified until the stream reaches the work.
@@ -55,7 +57,8 @@
  *     16-byte alignment of the pointers and of the row pitch enables 128-bit
  *     loads and stores.
  *   - Functions are reentrant and keep no mutable global state apart from a
- *     per-device compute-unit count cached on first use.
+ *     per-device compute-unit count and a per-device address of the
+ *     edge_batch_noalloc workspace, each cached on first use.
  */
 #ifndef EDGE_MASKS_H
 #define EDGE_MASKS_H
@@ -275,6 +278,30 @@ int edge_batch(const void* in_arena, void* out_arena, int64_t arena_words,
                const edge_image_desc* table_dev, int32_t n_images, int word_bits,
                int border, int mode, uint32_t flags, const edge_launch_cfg* cfg,
                void* workspace_dev, int64_t workspace_bytes, void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): edge_batch
+ * with the workspace held by the library. The work plan goes into a fixed
+ * device array in the library's code object, 256-byte aligned, one per GPU
+ * (about 0.4 MiB each, held until the process ends), sized for at most
+ * EDGE_BATCH_NOALLOC_MAX_IMAGES images; its device address is looked up
+ * once per GPU, on the first call with that GPU current.
+ *   Arguments as edge_batch, without the workspace. The current device must
+ *   be the one the arenas, the table and hip_stream belong to.
+ *   n_images > EDGE_BATCH_NOALLOC_MAX_IMAGES returns EDGE_ERR_WORKSPACE,
+ *   and EDGE_FLAG_PLANNED returns EDGE_ERR_INVALID (there is no way to put
+ *   a host plan into the array without a copy), both before any HIP call.
+ *   Allocates nothing: no hipMalloc, hipFree or allocating library call.
+ *   Every call on a GPU shares that GPU's array: the device planner
+ *   rewrites every word the kernel reads on each call, so nothing has to be
+ *   cleared between calls, but calls that overlap in time on one GPU (other
+ *   streams, other threads) race on the plan and give wrong output; order
+ *   them on one stream or with events. */
+#define EDGE_BATCH_NOALLOC_MAX_IMAGES 16384
+int edge_batch_noalloc(const void* in_arena, void* out_arena, int64_t arena_words,
+                       const edge_image_desc* table_dev, int32_t n_images, int word_bits,
+                       int border, int mode, uint32_t flags, const edge_launch_cfg* cfg,
+                       void* hip_stream);
 
 /* Capture the work of one edge_batch call (same arguments) into an
  * instantiated HIP graph. *graph_out receives an opaque handle. */

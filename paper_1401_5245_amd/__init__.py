@@ -232,4 +232,4 @@ def copy_bytes(src: torch.Tensor, dst: torch.Tensor, n_bytes: int, stream=None) 
 
 
 from .batch import (Batch, BatchGraph, batch_workspace_bytes, edge_batch,  # noqa: E402,F401
-                    pack_arena)
+                    edge_batch_noalloc, pack_arena)

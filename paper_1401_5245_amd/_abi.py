@@ -29,6 +29,7 @@ EDGE_FLAG_PLANNED = 1 << 2
 EDGE_FLAG_PEEL_EDGE = 1 << 3
 EDGE_PEEL_MAX_ITERATIONS = 30
 EDGE_MAX_HEIGHT = 1 << 30
+EDGE_BATCH_NOALLOC_MAX_IMAGES = 16384
 
 c_i32, c_i64, c_u32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p
 
@@ -90,6 +91,9 @@ _SIGNATURES = {
     "edge_batch": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i32, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_int, c_u32, ctypes.POINTER(EdgeLaunchCfg), c_vp, c_i64,
                                   c_vp]),
+    "edge_batch_noalloc": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i32, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, c_u32,
+                                          ctypes.POINTER(EdgeLaunchCfg), c_vp]),
     "edge_batch_plan": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp, c_i32, ctypes.c_int,
                                        ctypes.POINTER(EdgeLaunchCfg), c_vp, c_i64,
                                        ctypes.POINTER(c_i64)]),

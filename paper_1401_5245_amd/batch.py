@@ -125,6 +125,8 @@ def _check_batch_tensors(in_arena, out_arena, table_dev, n_images, workspace) ->
     descriptors, all contiguous device tensors."""
     for name, t in (("in_arena", in_arena), ("out_arena", out_arena), ("table", table_dev),
                     ("workspace", workspace)):
+        if t is None and name == "workspace":
+            continue
         if not (t.is_cuda and t.is_contiguous()):
             raise ValueError(f"{name} must be a contiguous device tensor")
     if out_arena.dtype != in_arena.dtype or out_arena.numel() != in_arena.numel():
@@ -149,6 +151,23 @@ def edge_batch(in_arena: torch.Tensor, out_arena: torch.Tensor, table_dev: torch
                           _flags(clause2_only, invert, planned), _cfg_ptr(cfg),
                           workspace.data_ptr(),
                           workspace.numel() * workspace.element_size(), stream_handle(stream)))
+
+
+def edge_batch_noalloc(in_arena: torch.Tensor, out_arena: torch.Tensor, table_dev: torch.Tensor,
+                       n_images: int, *, border: str = "white", mode: str = "masks",
+                       clause2_only: bool = False, invert: bool = False, cfg=None,
+                       stream=None) -> None:
+    """edge_batch with the workspace held by the library (a fixed array per
+    GPU, at most EDGE_BATCH_NOALLOC_MAX_IMAGES images): for callers that
+    cannot allocate. Calls that overlap in time on one GPU race."""
+    from . import stream_handle
+    wb = _word_bits(in_arena)
+    _check_batch_tensors(in_arena, out_arena, table_dev, n_images, None)
+    cfg = _resolve(cfg, n_images, in_arena.numel(), wb, mode)
+    check(_lib.edge_batch_noalloc(in_arena.data_ptr(), out_arena.data_ptr(), in_arena.numel(),
+                                  table_dev.data_ptr(), n_images, wb, _BORDERS[border],
+                                  _MODES[mode], _flags(clause2_only, invert), _cfg_ptr(cfg),
+                                  stream_handle(stream)))
 
 
 class BatchGraph:

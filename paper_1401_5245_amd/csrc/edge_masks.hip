@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <new>
 #include <stdint.h>
 #include <string.h>
@@ -80,7 +81,11 @@ constexpr int64_t kPlanMagic = 0x45444745504c414ell;   // "EDGEPLAN"
 constexpr int kMaxBatchBlocks = 65536;
 constexpr int kPlanThreads = 1024;
 
-__host__ __device__ inline int64_t ws_block_map_offset(int32_t n) { return kWsHeader + (int64_t)n + 1; }
+__host__ __device__ constexpr int64_t ws_block_map_offset(int32_t n) { return kWsHeader + (int64_t)n + 1; }
+// Workspace bytes for n descriptors (the block map sized for the largest grid).
+__host__ __device__ constexpr int64_t ws_bytes(int32_t n) {
+    return ws_block_map_offset(n) * 8 + (int64_t)kMaxBatchBlocks * 4;
+}
 
 // Units of descriptor d (0 when it fails the checks; *bad counts those).
 __device__ __forceinline__ int64_t desc_units(const edge_image_desc& d, int64_t arena_words,
@@ -546,8 +551,7 @@ int batch_validate(const void* in_arena, void* out_arena, int64_t arena_words,
     const uint64_t bytes = (uint64_t)arena_words * word_bytes;
     if (ranges_overlap((uintptr_t)in_arena, bytes, (uintptr_t)out_arena, bytes))
         return EDGE_ERR_ALIAS;
-    const int64_t need = edge_batch_workspace_bytes(n_images);
-    if (!workspace_dev || workspace_bytes < need || (uintptr_t)workspace_dev % 256)
+    if (!workspace_dev || workspace_bytes < ws_bytes(n_images) || (uintptr_t)workspace_dev % 256)
         return EDGE_ERR_WORKSPACE;
     a->in = in_arena;
     a->out = out_arena;
@@ -616,6 +620,47 @@ struct EdgeGraph {
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
+
+// ------------------------------------------------- library-held workspace ---
+
+// The workspace of edge_batch_noalloc: a fixed device array, one instance
+// per GPU the code object is loaded on, sized for the largest batch that
+// entry point accepts. Host code never passes the array's name to a kernel
+// or a copy (on the host it is only a stand-in for the device symbol); it
+// uses the device address looked up per device by noalloc_workspace().
+}  // namespace
+
+constexpr int64_t kNoAllocBytes = ws_bytes(EDGE_BATCH_NOALLOC_MAX_IMAGES);
+static_assert(kNoAllocBytes % 8 == 0 && kNoAllocBytes <= (1 << 20),
+              "a modest fixed workspace: at most 1 MiB per GPU");
+static __device__ __align__(256) int64_t g_noalloc_ws[kNoAllocBytes / 8];
+
+namespace {
+
+std::atomic<void*> g_noalloc_addr[kMaxDevices];
+std::mutex g_noalloc_mu;
+
+// Device address of the current device's array (hipGetSymbolAddress once
+// per device, with that device current; later calls read the cache).
+int noalloc_workspace(void** addr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_failed(e);
+    if (dev < 0 || dev >= kMaxDevices) return EDGE_ERR_UNSUPPORTED;
+    void* p = g_noalloc_addr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        p = g_noalloc_addr[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_noalloc_ws));
+            if (e != hipSuccess) return hip_failed(e);
+            if (!p || (uintptr_t)p % 256) return EDGE_ERR_WORKSPACE;
+            g_noalloc_addr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *addr = p;
+    return EDGE_OK;
+}
 
 // Built-in peel shape, from sweeps at 8192^2 and 16384^2: a unit walks
 // 2 * levels halo rows besides its strip (the first half of them with few
@@ -921,7 +966,7 @@ int edge_default_cfg(int64_t height, int64_t width, int word_bits, int mode, int
 
 int64_t edge_batch_workspace_bytes(int32_t n_images) {
     if (n_images < 0) return EDGE_ERR_INVALID;
-    return ws_block_map_offset(n_images) * 8 + (int64_t)kMaxBatchBlocks * 4;
+    return ws_bytes(n_images);
 }
 
 int edge_batch_check(const edge_image_desc* table_host, int32_t n_images, int64_t arena_words,
@@ -991,6 +1036,24 @@ int edge_batch(const void* in_arena, void* out_arena, int64_t arena_words,
                             border, mode, flags, cfg, workspace_dev, workspace_bytes, &a);
     if (rc) return rc;
     if (n_images == 0) return EDGE_OK;
+    return batch_enqueue(a, (hipStream_t)hip_stream);
+}
+
+int edge_batch_noalloc(const void* in_arena, void* out_arena, int64_t arena_words,
+                       const edge_image_desc* table_dev, int32_t n_images, int word_bits,
+                       int border, int mode, uint32_t flags, const edge_launch_cfg* cfg,
+                       void* hip_stream) {
+    if (n_images > EDGE_BATCH_NOALLOC_MAX_IMAGES) return EDGE_ERR_WORKSPACE;
+    if (flags & EDGE_FLAG_PLANNED) return EDGE_ERR_INVALID;
+    // every argument check first (with a stand-in workspace of the right
+    // size and alignment), then the one HIP query for the array's address
+    BatchArgs a;
+    int rc = batch_validate(in_arena, out_arena, arena_words, table_dev, n_images, word_bits,
+                            border, mode, flags, cfg, (void*)(uintptr_t)256, kNoAllocBytes, &a);
+    if (rc) return rc;
+    if (n_images == 0) return EDGE_OK;
+    rc = noalloc_workspace(&a.ws);
+    if (rc) return rc;
     return batch_enqueue(a, (hipStream_t)hip_stream);
 }
 

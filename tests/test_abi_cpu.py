@@ -174,6 +174,27 @@ def test_batch_validation():
     assert lib.edge_graph_launch(None, None) == INVALID
 
 
+def test_batch_noalloc_validation():
+    # every case returns before the one HIP query (the array's address)
+    W = 0x30000000
+    PLANNED = 1 << 2
+
+    def noalloc(inp=A, out=B, words=1000, tab=W + 0x1000, n=4, wb=32, border=0, mode=0, flags=0):
+        return lib.edge_batch_noalloc(inp, out, words, tab, n, wb, border, mode, flags, None, None)
+
+    assert _abi.EDGE_BATCH_NOALLOC_MAX_IMAGES == 16384
+    assert noalloc(n=16385) == WS
+    assert noalloc(n=1 << 30) == WS
+    assert noalloc(flags=PLANNED) == INVALID
+    assert noalloc(n=-1) == INVALID
+    assert noalloc(wb=8) == INVALID
+    assert noalloc(tab=None) == INVALID
+    assert noalloc(inp=A + 2) == ALIGN
+    assert noalloc(out=A + 400) == ALIAS
+    assert noalloc(n=0) == OK
+    assert noalloc(n=0, flags=PLANNED) == INVALID
+
+
 def test_copy_validation():
     assert lib.edge_copy_bytes(A, B, 15, None) == INVALID
     assert lib.edge_copy_bytes(A + 8, B, 16, None) == ALIGN
