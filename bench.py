@@ -66,6 +66,8 @@ def parse(argv=None):
     p.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
                    help="file the full results of every section are written to")
     p.add_argument("--verbose", action="store_true", help="per-step progress on stderr")
+    p.add_argument("--serve-copy", choices=("sdma", "kernel"), default="kernel",
+                   help="host copies of the server: the copy kernel (default) or hipMemcpyAsync")
     p.add_argument("--serve-only", action="store_true",
                    help="run only the serving sweep (prints its JSON)")
     p.add_argument("--batch-only", action="store_true",
@@ -675,7 +677,7 @@ def sustained(runs, p99_bound_ms):
     return best, later
 
 
-def serving(torch, em, p99_bound_ms=20.0, budget=4 << 30):
+def serving(torch, em, p99_bound_ms=20.0, budget=4 << 30, copy="kernel"):
     """Poisson request stream over a 64-image pool (sides log-uniform in
     [64, 4096], half glyph pages, half Bernoulli(0.3)); sweep the offered
     rate for the batched server and the per-request-launch server; report
@@ -690,12 +692,14 @@ def serving(torch, em, p99_bound_ms=20.0, budget=4 << 30):
         packed.append((pack_rows(im, 64, wd + wd % 2), im.shape[1]))
     pool = Pool.from_images(packed, 64)
     mean_px = float(pool.pixels.mean())
-    srv = Server(pool, budget, max_inflight=3)
+    srv = Server(pool, budget, max_inflight=3, copy=copy)
     rng = np.random.default_rng(55)
     out = {"workload": "serving: Poisson arrivals, 64-image pinned ingress ring (sides "
                        "log-uniform [64,4096], half glyph / half Bernoulli(0.3)), uint64; HBM "
                        "budget %d GiB, 3 batches in flight; latency = result in host memory "
-                       "- scheduled arrival" % (budget >> 30),
+                       "- scheduled arrival; host copies by %s" % (
+                           budget >> 30, "the copy kernel" if copy == "kernel" else
+                           "hipMemcpyAsync"),
            "mean_mpx_per_request": round(mean_px / 1e6, 3), "p99_bound_ms": p99_bound_ms}
     for name, per_req, rates in (("batched", False, (1e4, 2e4, 4e4, 8e4, 1.6e5, 2.4e5, 3.2e5,
                                                      4.8e5, 6.4e5)),
@@ -1138,7 +1142,7 @@ SUMMARY_SECTIONS = {
     "plain_65536": lambda torch, em, tm, a: plain_65536(torch, em, tm, 20),
     "full_65536": lambda torch, em, tm, a: full_65536(torch, em, tm),
     "batched_4096": lambda torch, em, tm, a: batched_crops(torch, em, tm, 200),
-    "serving": lambda torch, em, tm, a: serving(torch, em),
+    "serving": lambda torch, em, tm, a: serving(torch, em, copy=a.serve_copy),
 }
 # Sections written to the detail file only.
 DETAIL_SECTIONS = {

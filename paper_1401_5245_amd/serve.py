@@ -6,18 +6,28 @@ arena (the HBM budget) has room, copies each admitted group to the device
 with as few copies as the layout allows, and whenever a launch slot is free
 sends every admitted request not yet launched into one persistent batched
 launch (``edge_batch``). Up to ``max_inflight`` batches are on the device at
-once, each moving through three streams: copy-in, compute, copy-out; a
-batch's arena space is released when its results are back in host memory,
-and the next arrivals are admitted into it. Latency is measured from a
-request's scheduled arrival to the moment its result is in host memory.
+once, each moving through three streams: copy-in, compute, copy-out.
+Results come back into a pinned host ring laid out like the device arena,
+so each request has its own output slice for as long as its arena block is
+live; a batch's block is released once its results are in host memory
+(and, with ``record_outputs``, copied out of the ring), and the next
+arrivals are admitted into it. Latency is measured from a request's
+scheduled arrival to the moment its result is in host memory.
 
-``per_request=True`` runs the same loop with one plain ``edge_masks``
+Copies between pinned host memory and the arena go either through the
+runtime's copy engines (``copy="sdma"``: hipMemcpyAsync) or through the
+library's 128-bit copy kernel reading and writing the pinned host memory
+directly (``copy="kernel"``: edge_copy_bytes), an ordinary kernel launch on
+the copy streams.
+
+``per_request=True`` runs the same loop with one plain ``edge_image``
 launch (and its own copy-out) per request: the per-request-launch server
 that batching is compared against.
 """
 from __future__ import annotations
 
 import collections
+import ctypes
 import time
 from dataclasses import dataclass, field
 
@@ -25,42 +35,107 @@ import numpy as np
 import torch
 
 from . import batch as _batch
-from ._abi import EdgeError, EDGE_ERR_INVALID
+from ._abi import EdgeError, EDGE_ERR_INVALID, check, load
 
 _HIP = None
+_HIP_MEMCPY_DEFAULT = 4     # direction inferred from the pointers (unified addressing)
+_HIP_EVENT_DISABLE_TIMING = 2
+_HIP_ERROR_NOT_READY = 600
 
 
 def _hip():
-    """The HIP runtime already loaded by torch (copies are issued with
-    hipMemcpyAsync directly: torch's non-blocking copies into pinned memory
-    also record a tracking event per copy, which can stall the host)."""
+    """The HIP runtime already loaded by torch. Copies, events and waits go
+    to it directly: torch's non-blocking copies into pinned memory also
+    record a tracking event per copy, which can stall the host. ctypes
+    releases the GIL for the duration of each call."""
     global _HIP
     if _HIP is None:
-        import ctypes
         lib = ctypes.CDLL("libamdhip64.so")
-        lib.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
-                                       ctypes.c_int, ctypes.c_void_p]
-        lib.hipMemcpyAsync.restype = ctypes.c_int
+        vp = ctypes.c_void_p
+        for name, args in (("hipMemcpyAsync", [vp, vp, ctypes.c_size_t, ctypes.c_int, vp]),
+                           ("hipEventCreateWithFlags", [ctypes.POINTER(vp), ctypes.c_uint]),
+                           ("hipEventRecord", [vp, vp]),
+                           ("hipStreamWaitEvent", [vp, vp, ctypes.c_uint]),
+                           ("hipEventQuery", [vp]),
+                           ("hipEventDestroy", [vp]),
+                           ("hipHostGetDevicePointer", [ctypes.POINTER(vp), vp, ctypes.c_uint])):
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
         _HIP = lib
     return _HIP
 
 
-_HIP_MEMCPY_DEFAULT = 4     # direction inferred from the pointers (unified addressing)
+def _hip_ok(rc: int, what: str) -> None:
+    if rc != 0:
+        raise RuntimeError(f"{what} failed (hipError {rc})")
 
 
 def _copy_async(dst: torch.Tensor, dst_off: int, src: torch.Tensor, src_off: int, n: int,
-                stream: torch.cuda.Stream) -> None:
-    """Copy n elements src[src_off:] -> dst[dst_off:] on `stream`."""
+                stream) -> None:
+    """Copy n elements src[src_off:] -> dst[dst_off:] on `stream` (a torch
+    stream or a raw hipStream_t handle)."""
     if not (0 <= src_off and src_off + n <= src.numel() and 0 <= dst_off
             and dst_off + n <= dst.numel()):
         raise ValueError("copy outside its tensors")
     if dst.element_size() != src.element_size():
         raise ValueError("source and destination differ in element size")
     es = src.element_size()
-    rc = _hip().hipMemcpyAsync(dst.data_ptr() + dst_off * es, src.data_ptr() + src_off * es,
-                               n * es, _HIP_MEMCPY_DEFAULT, stream.cuda_stream)
-    if rc != 0:
-        raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+    handle = stream if isinstance(stream, int) else stream.cuda_stream
+    _hip_ok(_hip().hipMemcpyAsync(dst.data_ptr() + dst_off * es, src.data_ptr() + src_off * es,
+                                  n * es, _HIP_MEMCPY_DEFAULT, handle), "hipMemcpyAsync")
+
+
+def _device_mapped(t: torch.Tensor) -> bool:
+    """True when pinned host tensor t is mapped into the device's address
+    space at its own address (what a kernel reading it directly needs)."""
+    d = ctypes.c_void_p()
+    if _hip().hipHostGetDevicePointer(ctypes.byref(d), t.data_ptr(), 0) != 0:
+        return False
+    return d.value == t.data_ptr()
+
+
+def _copy_kernel(dst: torch.Tensor, dst_off: int, src: torch.Tensor, src_off: int, n: int,
+                 stream: int) -> None:
+    """The same copy with the library's copy kernel (edge_copy_bytes): 16-byte
+    aligned ends and a multiple of 16 bytes, host side pinned."""
+    if not (0 <= src_off and src_off + n <= src.numel() and 0 <= dst_off
+            and dst_off + n <= dst.numel()):
+        raise ValueError("copy outside its tensors")
+    es = src.element_size()
+    check(load().edge_copy_bytes(src.data_ptr() + src_off * es, dst.data_ptr() + dst_off * es,
+                                 n * es, stream))
+
+
+class _Event:
+    """A raw HIP event (no timing), re-recorded on every use."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _hip_ok(_hip().hipEventCreateWithFlags(ctypes.byref(h), _HIP_EVENT_DISABLE_TIMING),
+                "hipEventCreateWithFlags")
+        self.h = h
+
+    def record(self, stream: int) -> None:
+        _hip_ok(_hip().hipEventRecord(self.h, stream), "hipEventRecord")
+
+    def wait_on(self, stream: int) -> None:
+        """Make `stream` wait for the last record of this event."""
+        _hip_ok(_hip().hipStreamWaitEvent(stream, self.h, 0), "hipStreamWaitEvent")
+
+    def done(self) -> bool:
+        rc = _hip().hipEventQuery(self.h)
+        if rc == _HIP_ERROR_NOT_READY:
+            return False
+        _hip_ok(rc, "hipEventQuery")
+        return True
+
+    def __del__(self):
+        try:
+            if self.h:
+                _hip().hipEventDestroy(self.h)
+        except Exception:
+            pass
 
 
 class RingArena:
@@ -133,10 +208,9 @@ class Pool:
     """Packed request images in one pinned host buffer.
 
     host_in: pinned words of every pool image back to back (16-byte aligned
-    offsets); host_out: pinned buffer of the same layout for results.
+    offsets).
     """
     host_in: torch.Tensor
-    host_out: torch.Tensor
     table: np.ndarray                # DESC_DTYPE, offsets into host_in
     word_bits: int
     pixels: np.ndarray               # H*W per image
@@ -146,9 +220,8 @@ class Pool:
         arena, table = _batch.pack_arena(packed, word_bits)
         view = np.int64 if word_bits == 64 else np.int32
         host_in = torch.from_numpy(arena.view(view)).pin_memory()
-        host_out = torch.zeros_like(host_in).pin_memory()
         pixels = table["height"].astype(np.int64) * table["width"].astype(np.int64)
-        return cls(host_in, host_out, table, word_bits, pixels)
+        return cls(host_in, table, word_bits, pixels)
 
     def words(self, i: int) -> int:
         d = self.table[i]
@@ -159,8 +232,8 @@ class Pool:
 class _Batch:
     reqs: list
     slot: int
-    ev_kernel: object
-    ev_done: object
+    ev_kernel: _Event
+    ev_done: _Event
 
 
 @dataclass
@@ -198,13 +271,17 @@ def _runs(src_offs, dst_offs, sizes):
     return runs
 
 
+
+
 class Server:
     """One-GPU continuous-batching server over a pinned request pool."""
 
     def __init__(self, pool: Pool, budget_bytes: int, *, max_inflight: int = 3,
                  max_batch: int = 4096, max_batch_bytes: int = 64 << 20,
                  border: str = "white", mode: str = "masks",
-                 cfg=None, device="cuda"):
+                 cfg=None, copy: str = "kernel", device="cuda"):
+        if copy not in ("sdma", "kernel"):
+            raise ValueError("copy must be 'sdma' or 'kernel'")
         self.pool = pool
         wb = pool.word_bits
         self.word_bytes = wb // 8
@@ -215,42 +292,57 @@ class Server:
         dt = torch.int64 if wb == 64 else torch.int32
         self.dev_in = torch.zeros(cap, dtype=dt, device=device)
         self.dev_out = torch.zeros(cap, dtype=dt, device=device)
+        # results land in a pinned host ring with the device arena's layout:
+        # a request's output slice is its own until its block is released
+        self.host_out = torch.zeros(cap, dtype=dt).pin_memory()
         self.max_inflight = max_inflight
         self.max_batch = max_batch
         # bytes of input per batch: a burst of arrivals then becomes several
         # pipelined batches instead of one whose copies hold up the rest
         self.max_batch_words = max(1, int(max_batch_bytes) // self.word_bytes)
         self.kw = dict(border=border, mode=mode, cfg=cfg)
+        self.copy_engine = copy
+        self._copy = _copy_kernel if copy == "kernel" else _copy_async
         self.s_in = torch.cuda.Stream(device)
         self.s_k = torch.cuda.Stream(device)
         self.s_out = torch.cuda.Stream(device)
+        self.h_in, self.h_k, self.h_out = (self.s_in.cuda_stream, self.s_k.cuda_stream,
+                                           self.s_out.cuda_stream)
         nb = _batch.batch_workspace_bytes(max_batch)
+        # table and plan are copied in whole 16-byte units (the kernel copy's
+        # granule): one spare word past the largest size each
         self.slots = []
         for _ in range(max_inflight):
             self.slots.append({
-                "table_host": torch.zeros(max_batch * 3, dtype=torch.int64).pin_memory(),
-                "table_dev": torch.zeros(max_batch * 3, dtype=torch.int64, device=device),
-                "plan_host": torch.zeros(-(-nb // 8), dtype=torch.int64).pin_memory(),
-                "ws": torch.zeros(-(-nb // 8), dtype=torch.int64, device=device),
+                "table_host": torch.zeros(max_batch * 3 + 1, dtype=torch.int64).pin_memory(),
+                "table_dev": torch.zeros(max_batch * 3 + 1, dtype=torch.int64, device=device),
+                "plan_host": torch.zeros(-(-nb // 8) + 1, dtype=torch.int64).pin_memory(),
+                "ws": torch.zeros(-(-nb // 8) + 1, dtype=torch.int64, device=device),
                 # created once and re-recorded each time the slot is used: the
                 # slot is reused only after its last batch is back on the host
-                "ev_in": torch.cuda.Event(), "ev_k": torch.cuda.Event(),
-                "ev_d": torch.cuda.Event(),
+                "ev_in": _Event(), "ev_k": _Event(), "ev_d": _Event(),
                 "busy": False})
         self._tab = np.zeros(max_batch, dtype=_batch.DESC_DTYPE)
+        if copy == "kernel":
+            host = [self.pool.host_in, self.host_out] + [
+                S[k] for S in self.slots for k in ("table_host", "plan_host")]
+            if not all(t.is_pinned() and _device_mapped(t) for t in host):
+                raise RuntimeError("copy='kernel' needs pinned host buffers mapped at their "
+                                   "own address on the device")
         self.warmup()
 
     def warmup(self):
-        """Run the copy paths once at full size (pool to arena and back, on
-        the serving streams) so that first-use set-up in the runtime is not
-        paid by a request."""
+        """Run the copy paths once at full size (pool to arena, arena to the
+        host ring, on the serving streams) so that first-use set-up in the
+        runtime is not paid by a request."""
         n = min(self.pool.host_in.numel(), self.dev_in.numel())
-        _copy_async(self.dev_in, 0, self.pool.host_in, 0, n, self.s_in)
+        n -= n % (16 // self.word_bytes)
+        self._copy(self.dev_in, 0, self.pool.host_in, 0, n, self.h_in)
         self.s_out.wait_stream(self.s_in)
-        _copy_async(self.pool.host_out, 0, self.dev_in, 0, n, self.s_out)
+        self._copy(self.host_out, 0, self.dev_in, 0, n, self.h_out)
         for S in self.slots:
             for k in ("ev_in", "ev_k", "ev_d"):
-                S[k].record(self.s_out)
+                S[k].record(self.h_out)
         torch.cuda.synchronize()
 
     # ---------------------------------------------------------------- loop --
@@ -281,7 +373,8 @@ class Server:
         nbatches = 0
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0  # noqa: E731
-        dev_in, dev_out, host_in, host_out = self.dev_in, self.dev_out, pool.host_in, pool.host_out
+        dev_in, dev_out, host_in, host_out = self.dev_in, self.dev_out, pool.host_in, self.host_out
+        copy = self._copy
         table = pool.table
         rejected = 0
         # host-side stalls: the longest pass through the loop, and the most a
@@ -299,19 +392,18 @@ class Server:
             progressed = False
             it = now()
             # 1. completions, oldest first (the ring frees in order)
-            while inflight and inflight[0].ev_done.query():
+            while inflight and inflight[0].ev_done.done():
                 b = inflight.popleft()
                 t = now()
                 for r in b.reqs:
                     r.done = t
-                    self.ring.free_oldest()
                     if record_outputs:
-                        o = int(table[r.pool_index]["offset_words"])
-                        out_of[r.rid] = host_out[o:o + words[r.rid]].clone()
+                        out_of[r.rid] = host_out[r.offset:r.offset + words[r.rid]].clone()
+                    self.ring.free_oldest()
                 self.slots[b.slot]["busy"] = False
                 progressed = True
             for b in inflight:
-                if b.reqs[0].kernel_done < 0 and b.ev_kernel.query():
+                if b.reqs[0].kernel_done < 0 and b.ev_kernel.done():
                     t = now()
                     for r in b.reqs:
                         r.kernel_done = t
@@ -337,10 +429,13 @@ class Server:
                 waiting.popleft()
                 newly.append(r)
             if newly:
+                # whole 16-byte units (the ring's and the pool's alignment):
+                # neighbouring blocks then merge into one copy
                 runs = _runs([int(table[r.pool_index]["offset_words"]) for r in newly],
-                             [r.offset for r in newly], [int(words[r.rid]) for r in newly])
+                             [r.offset for r in newly],
+                             [self.ring._round(words[r.rid]) for r in newly])
                 for s, d, m in runs:
-                    _copy_async(dev_in, d, host_in, s, m, self.s_in)
+                    copy(dev_in, d, host_in, s, m, self.h_in)
                 admitted.extend(newly)
                 progressed = True
             # 3. launch: every admitted request not yet launched (continuous batching)
@@ -360,58 +455,52 @@ class Server:
                     S = self.slots[slot]
                     # the copy-in stream is in order: one event recorded now
                     # covers the copies of every request admitted so far
-                    S["ev_in"].record(self.s_in)
-                    self.s_k.wait_event(S["ev_in"])
+                    S["ev_in"].record(self.h_in)
+                    S["ev_in"].wait_on(self.h_k)
                     t = now()
                     t_s = mark("launch_wait", t_s)
-                    with torch.cuda.stream(self.s_k):
-                        if per_request:
-                            r = group[0]
-                            d = table[r.pool_index]
-                            H, W, St = int(d["height"]), int(d["width"]), int(d["stride_words"])
-                            m = int(words[r.rid])
-                            em.edge_image(dev_in[r.offset:r.offset + m],
-                                          dev_out[r.offset:r.offset + m], H, W,
-                                          stride_words=St, border=self.kw["border"],
-                                          mode=self.kw["mode"], stream=self.s_k)
-                        else:
-                            k = len(group)
-                            tab = self._tab[:k]
-                            pidx = np.fromiter((r.pool_index for r in group), np.int64, k)
-                            tab["offset_words"] = np.fromiter((r.offset for r in group),
-                                                              np.int64, k)
-                            tab["height"] = table["height"][pidx]
-                            tab["width"] = table["width"][pidx]
-                            tab["stride_words"] = table["stride_words"][pidx]
-                            th = S["table_host"]
-                            th[:k * 3].numpy()[:] = tab.view(np.int64)
-                            ph = S["plan_host"]
-                            _, used = _batch.plan_batch(dev_in, dev_out, tab,
-                                                        mode=self.kw["mode"],
-                                                        cfg=self.kw["cfg"], out=ph.numpy())
-                            nw = -(-used // 8)
-                            t_s = mark("plan", t_s)
-                            _copy_async(S["table_dev"], 0, th, 0, k * 3, self.s_k)
-                            _copy_async(S["ws"], 0, ph, 0, nw, self.s_k)
-                            t_s = mark("plan_copy", t_s)
-                            _batch.edge_batch(dev_in, dev_out, S["table_dev"], k, S["ws"],
-                                              planned=True, stream=self.s_k, **self.kw)
-                            t_s = mark("batch_launch", t_s)
-                        ev_k = S["ev_k"]
-                        ev_k.record(self.s_k)
-                    self.s_out.wait_event(ev_k)
-                    runs = _runs([r.offset for r in group],
-                                 [int(table[r.pool_index]["offset_words"]) for r in group],
-                                 [int(words[r.rid]) for r in group])
-                    for s, d, m in runs:
-                        _copy_async(host_out, d, dev_out, s, m, self.s_out)
-                    ev_d = S["ev_d"]
-                    ev_d.record(self.s_out)
+                    if per_request:
+                        r = group[0]
+                        d = table[r.pool_index]
+                        m = int(words[r.rid])
+                        em.edge_image(dev_in[r.offset:r.offset + m], dev_out[r.offset:r.offset + m],
+                                      int(d["height"]), int(d["width"]),
+                                      stride_words=int(d["stride_words"]),
+                                      border=self.kw["border"], mode=self.kw["mode"],
+                                      stream=self.s_k)
+                        t_s = mark("launch", t_s)
+                    else:
+                        k = len(group)
+                        tab = self._tab[:k]
+                        pidx = np.fromiter((r.pool_index for r in group), np.int64, k)
+                        tab["offset_words"] = np.fromiter((r.offset for r in group), np.int64, k)
+                        tab["height"] = table["height"][pidx]
+                        tab["width"] = table["width"][pidx]
+                        tab["stride_words"] = table["stride_words"][pidx]
+                        S["table_host"][:k * 3].numpy()[:] = tab.view(np.int64)
+                        _, used = _batch.plan_batch(dev_in, dev_out, tab, mode=self.kw["mode"],
+                                                    cfg=self.kw["cfg"],
+                                                    out=S["plan_host"].numpy())
+                        t_s = mark("plan", t_s)
+                        nt, nw = k * 3, -(-used // 8)
+                        copy(S["table_dev"], 0, S["table_host"], 0, nt + nt % 2, self.h_k)
+                        copy(S["ws"], 0, S["plan_host"], 0, nw + nw % 2, self.h_k)
+                        t_s = mark("plan_copy", t_s)
+                        _batch.edge_batch(dev_in, dev_out, S["table_dev"], k, S["ws"],
+                                          planned=True, stream=self.s_k, **self.kw)
+                        t_s = mark("launch", t_s)
+                    S["ev_k"].record(self.h_k)
+                    S["ev_k"].wait_on(self.h_out)
+                    # results to the same offsets of the host ring
+                    for s, d, m in _runs([r.offset for r in group], [r.offset for r in group],
+                                         [self.ring._round(words[r.rid]) for r in group]):
+                        copy(host_out, d, dev_out, s, m, self.h_out)
+                    S["ev_d"].record(self.h_out)
                     mark("copy_out", t_s)
                     for r in group:
                         r.launched = t
                     S["busy"] = True
-                    inflight.append(_Batch(group, slot, ev_k, ev_d))
+                    inflight.append(_Batch(group, slot, S["ev_k"], S["ev_d"]))
                     nbatches += 1
                     progressed = True
             t_end = now()
@@ -433,9 +522,9 @@ class Server:
         lat = np.array([(r.done - r.arrival) * 1e3 for r in served])
         lat_k = np.array([((r.kernel_done if r.kernel_done >= 0 else r.done) - r.arrival) * 1e3
                           for r in served])
-        queue = np.array([(r.launched - r.arrival) * 1e3 for r in served])
-        # stages: waiting for a launch slot (and its copy-in), copy-in + kernel
-        # as seen by the host, copy-out
+        queue_ms = np.array([(r.launched - r.arrival) * 1e3 for r in served])
+        # stages: waiting for a launch slot (and its copy-in), copy-in +
+        # kernel as seen by the host, copy-out
         k_seen = np.array([((r.kernel_done if r.kernel_done >= 0 else r.done) - r.launched) * 1e3
                            for r in served])
         d2h = np.array([(r.done - (r.kernel_done if r.kernel_done >= 0 else r.done)) * 1e3
@@ -447,10 +536,10 @@ class Server:
         pct = (lambda a, p: round(float(np.percentile(a, p)), 3) if a.size else None)
         stages = {"launch_to_kernel_done_ms": [pct(k_seen, 50), pct(k_seen, 99)],
                   "copy_out_ms": [pct(d2h, 50), pct(d2h, 99)],
-                  "queue_ms": [pct(queue, 50), pct(queue, 99)]}
+                  "queue_ms": [pct(queue_ms, 50), pct(queue_ms, 99)]}
         dur = t_last - t_first
-        st = Stats(lat, lat_k, queue, pixels, dur, nbatches, rejected,
-                   {"stages_p50_p99": stages,
+        st = Stats(lat, lat_k, queue_ms, pixels, dur, nbatches, rejected,
+                   {"copy": self.copy_engine, "stages_p50_p99": stages,
                     "host_link_gbs_each_way": round(copied / dur / 1e9, 2) if dur > 0 else 0.0,
                     "max_loop_pass_ms": round(max_pass * 1e3, 3),
                     "max_oversleep_ms": round(max_oversleep * 1e3, 3),

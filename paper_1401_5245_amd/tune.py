@@ -3,9 +3,11 @@ wavefronts per workgroup, persistent workgroups per CU, cache policy).
 
 Each candidate is timed on the device from a captured graph of repeated
 launches (so host launch overhead does not decide), and is admitted only
-when its output equals, bit for bit, the output of the library's built-in
-configuration on the same input. Winners are cached in a JSON file keyed by
-GPU architecture, word size, mode and a size class.
+when its output equals, bit for bit, a reference output: the expected words
+the caller passes (its tests pass the CPU oracle's, packed), or else the
+output of the library's built-in configuration on the same input. Winners
+are cached in a JSON file keyed by GPU architecture, word size, mode and a
+size class.
 """
 from __future__ import annotations
 
@@ -136,17 +138,25 @@ def _rotate_time_us(fns, reps: int) -> float:
 
 def tune_image(inp, out, height, width, *, mode="masks", border="white", candidates=None,
                cache: TuneCache | None = None, launches=20, reps=3, cold_bytes=512 << 20,
-               verbose=False):
+               reference=None, verbose=False):
     """Time every candidate on (inp, out); keep the fastest whose output
-    equals the built-in configuration's. Returns (cfg, microseconds).
+    equals `reference` (a tensor like `out` holding the expected words, the
+    words out of the image's rows zero), or when it is None the output of
+    the built-in configuration. Returns (cfg, microseconds).
 
     Timing rotates over copies of the buffers until `cold_bytes` are
     touched per round, so images smaller than the last-level cache are
     timed from HBM, as a stream of distinct images would be."""
     import paper_1401_5245_amd as em
-    em.edge_image(inp, out, height, width, mode=mode, border=border)
-    torch.cuda.synchronize()
-    ref = out.clone()
+    if reference is None:
+        out.zero_()
+        em.edge_image(inp, out, height, width, mode=mode, border=border)
+        torch.cuda.synchronize()
+        ref = out.clone()
+    else:
+        if reference.shape != out.shape or reference.dtype != out.dtype:
+            raise ValueError("reference must match out in shape and type")
+        ref = reference.to(out.device)
     per_pair = 2 * inp.numel() * inp.element_size()
     copies = max(1, min(launches, -(-cold_bytes // per_pair)))
     ins = [inp] + [inp.clone() for _ in range(copies - 1)]
@@ -171,7 +181,7 @@ def tune_image(inp, out, height, width, *, mode="masks", border="white", candida
         if us < best_us:
             best, best_us = c, us
     if best is None:
-        raise RuntimeError("no candidate configuration matched the built-in output")
+        raise RuntimeError("no candidate configuration matched the reference output")
     if cache is not None:
         cache.put(image_key(height, width, em.word_bits_of(inp), mode), best, best_us, tried)
     return best, best_us
@@ -187,16 +197,25 @@ def batch_candidates():
 
 
 def tune_batch(batch, *, candidates=None, cache: TuneCache | None = None, launches=10, reps=3,
-               verbose=False):
-    """Tune the persistent batch launch of a Batch (its table and arenas).
-    Returns (cfg, microseconds per batched launch)."""
+               reference=None, verbose=False):
+    """Tune the persistent batch launch of a Batch (its table and arenas):
+    keep the fastest candidate whose output arena equals `reference` (a
+    tensor like batch.out, zero outside the images' rows), or when it is
+    None the output of the built-in configuration. Returns (cfg,
+    microseconds per batched launch)."""
     from .batch import edge_batch, plan_batch
     kw = dict(batch.kw)
     kw.pop("cfg", None)
     kw.pop("planned", None)
-    edge_batch(batch.inp, batch.out, batch.table_dev, batch.n, batch.workspace, **kw)
-    torch.cuda.synchronize()
-    ref = batch.out.clone()
+    if reference is None:
+        batch.out.zero_()
+        edge_batch(batch.inp, batch.out, batch.table_dev, batch.n, batch.workspace, **kw)
+        torch.cuda.synchronize()
+        ref = batch.out.clone()
+    else:
+        if reference.shape != batch.out.shape or reference.dtype != batch.out.dtype:
+            raise ValueError("reference must match the output arena in shape and type")
+        ref = reference.to(batch.out.device)
     best, best_us, tried = None, float("inf"), 0
     ws = batch.workspace
     for c in (list(candidates) if candidates is not None else list(batch_candidates())):
@@ -226,7 +245,7 @@ def tune_batch(batch, *, candidates=None, cache: TuneCache | None = None, launch
                                  cfg=batch.kw.get("cfg"))
         ws[:-(-used // 8)].copy_(torch.from_numpy(words[:-(-used // 8)]))
     if best is None:
-        raise RuntimeError("no candidate configuration matched the built-in output")
+        raise RuntimeError("no candidate configuration matched the reference output")
     if cache is not None:
         total = int(batch.inp.numel())
         cache.put(batch_key(batch.n, total, batch.word_bits, kw.get("mode", "masks")), best,

@@ -35,7 +35,8 @@ def alone(img):
 
 @pytest.mark.parametrize("per_request", [False, True])
 @pytest.mark.parametrize("budget_kib", [64, 4096])
-def test_results_same_alone_and_in_mix(per_request, budget_kib):
+@pytest.mark.parametrize("copy", ["sdma", "kernel"])
+def test_results_same_alone_and_in_mix(per_request, budget_kib, copy):
     from paper_1401_5245_amd.serve import Server, poisson_arrivals
     imgs, pool = make_pool()
     singles = [alone(im) for im in imgs]
@@ -47,17 +48,21 @@ def test_results_same_alone_and_in_mix(per_request, budget_kib):
     need = (maxw + maxw % 2) * 8 * 2          # blocks are rounded to 16 bytes
     if need > budget:   # keep every request servable under the small budget
         budget = need
-    srv = Server(pool, budget, max_inflight=3)
-    log(f"serve per_request={per_request} budget={budget}")
+    srv = Server(pool, budget, max_inflight=3, copy=copy)
+    log(f"serve per_request={per_request} budget={budget} copy={copy}")
     st = srv.run(arrivals, idx, per_request=per_request, record_outputs=True)
     assert st.rejected == 0 and st.latencies_ms.size == n
     outs = st.extra["outputs"]
+    # every request's own output slice: equal to the image run alone, and
+    # every pool image's edge map equal to the oracle's
+    wants = [oracle.edge(im) for im in imgs]
+    for i in range(len(imgs)):
+        assert_same(unpack_rows(singles[i], imgs[i].shape[1]), wants[i], f"image {i} alone")
     for r in range(n):
         i = int(idx[r])
         got = outs[r].numpy().view(np.uint64).reshape(singles[i].shape)
         np.testing.assert_array_equal(got, singles[i], err_msg=f"request {r} (image {i})")
-    for i in set(int(v) for v in idx[:10]):
-        assert_same(unpack_rows(singles[i], imgs[i].shape[1]), oracle.edge(imgs[i]), f"image {i}")
+        assert_same(unpack_rows(got, imgs[i].shape[1]), wants[i], f"request {r} (image {i})")
     s = st.summary()
     assert s["p50_ms"] > 0 and s["p99_ms"] >= s["p50_ms"]
     if not per_request and budget_kib == 4096:
