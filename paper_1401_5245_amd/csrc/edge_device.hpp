@@ -1003,6 +1003,27 @@ __device__ __forceinline__ NarrowLanes narrow_lanes(const Geom& g, uint32_t bw) 
     return l;
 }
 
+// The same lane layout from a planned image: grp rows per step and the
+// quotient lane / wd as (lane * qmagic) >> 16 with qmagic = ceil(2^16 / wd)
+// (exact for lane < 64 and wd <= 32: the error is below 64 / 2^16, less than
+// the 1 / wd that separates lane / wd from the next integer). A lane whose
+// word index falls outside [0, wd), as an inconsistent plan could make it,
+// stays unused.
+__device__ __forceinline__ NarrowLanes narrow_lanes_q(const Geom& g, int grp, uint32_t qmagic,
+                                                      uint32_t bw) {
+    const int lane = threadIdx.x & (kWave - 1);
+    NarrowLanes l;
+    l.wd = g.wd;
+    l.grp = grp;
+    l.q = (int)(((uint32_t)lane * qmagic) >> 16);
+    const int j = lane - l.q * l.wd;
+    l.used = l.q < l.grp && j >= 0 && j < l.wd;
+    l.j = l.used ? j : 0;
+    l.vm = valid_bits(l.j, g.width);
+    l.om = bw & ~l.vm;
+    return l;
+}
+
 struct NarrowGroup {
     uint32_t c[kNarrowSteps], u[kNarrowSteps], d[kNarrowSteps];
 };
@@ -1073,14 +1094,19 @@ __device__ __forceinline__ void narrow_emit(const Geom& g, const NarrowLanes& l,
 }
 
 template <int MODE>
-__device__ __forceinline__ void narrow_unit(const Geom& g, int ya, int yb, uint32_t bw,
-                                            bool invert) {
-    const NarrowLanes l = narrow_lanes(g, bw);
+__device__ __forceinline__ void narrow_rows(const Geom& g, const NarrowLanes& l, int ya, int yb,
+                                            uint32_t bw, bool invert) {
     for (int y = ya; y < yb; y += l.grp * kNarrowSteps) {
         NarrowGroup r;
         narrow_load(g, l, ya, yb, y, r);
         narrow_emit<MODE>(g, l, yb, y, r, bw, invert);
     }
+}
+
+template <int MODE>
+__device__ __forceinline__ void narrow_unit(const Geom& g, int ya, int yb, uint32_t bw,
+                                            bool invert) {
+    narrow_rows<MODE>(g, narrow_lanes(g, bw), ya, yb, bw, invert);
 }
 
 // Vector width actually used for a wide image: the largest v <= vmax whose

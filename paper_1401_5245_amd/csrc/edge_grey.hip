@@ -13,9 +13,8 @@ using namespace edgek;
 // a barrier.
 template <int MODE, int RW, bool ALIGNED, class Pol>
 __global__ void __launch_bounds__(512) k_grey_band(Geom g, int64_t chunks, int64_t nunits,
-                                                   uint32_t bw, int invert) {
+                                                   uint32_t bw, int invert, int nw) {
     extern __shared__ uint32_t band_tile[];
-    const int nw = blockDim.x / kWave;
     for (int64_t unit = xcd_block(blockIdx.x, gridDim.x); unit < nunits; unit += gridDim.x) {
         const int64_t band = unit / chunks;
         const int64_t chunk = unit - band * chunks;
@@ -39,7 +38,7 @@ template <bool ALIGNED>
 __global__ void __launch_bounds__(256) k_pack(const uint8_t* grey, int64_t gstride, uint32_t* out,
                                               int64_t stride, int32_t height, int32_t width,
                                               int32_t wd, uint32_t thr) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;    // launched with 256 threads
     if (t >= (int64_t)height * wd) return;
     const int64_t y = t / wd;
     const int j = (int)(t - y * wd);
@@ -59,7 +58,7 @@ int launch_grey_band_rw(const Geom& g, int nw, int64_t chunks, uint32_t bw, int 
     const int64_t blocks = std::min<int64_t>(nunits, kMaxBandBlocks);
     const size_t lds = (size_t)nw * RW * kBandPitch * sizeof(uint32_t);
     hipLaunchKernelGGL((k_grey_band<MODE, RW, ALIGNED, Pol>), dim3((uint32_t)blocks),
-                       dim3(nw * kWave), lds, stream, g, chunks, nunits, bw, invert);
+                       dim3(nw * kWave), lds, stream, g, chunks, nunits, bw, invert, nw);
     return launch_status();
 }
 

@@ -23,10 +23,11 @@ static_assert(kMaxHeight == EDGE_MAX_HEIGHT, "one height limit for the header an
 // ================================================================ kernels ===
 
 // One image, strips of `rows` rows x 64*VW words, one wavefront per strip.
+// wpb: wavefronts per workgroup, passed in (reading the workgroup size
+// costs every wavefront a dependent load before its first unit).
 template <int VW, int MODE, class Pol>
 __global__ void __launch_bounds__(512) k_strip(Geom g, int64_t chunks, int rows, int64_t nunits,
-                                               uint32_t bw, int invert) {
-    const int wpb = blockDim.x / kWave;
+                                               uint32_t bw, int invert, int wpb) {
     const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
                          wave_uniform(threadIdx.x / kWave);
     if (unit >= nunits) return;
@@ -40,8 +41,7 @@ __global__ void __launch_bounds__(512) k_strip(Geom g, int64_t chunks, int rows,
 // One image with rows of <= 32 words, `band` rows per wavefront.
 template <int MODE>
 __global__ void __launch_bounds__(512) k_narrow(Geom g, int64_t band, int64_t nunits, uint32_t bw,
-                                                int invert) {
-    const int wpb = blockDim.x / kWave;
+                                                int invert, int wpb) {
     const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
                          wave_uniform(threadIdx.x / kWave);
     if (unit >= nunits) return;
@@ -70,21 +70,86 @@ __host__ __device__ static inline bool desc_ok(const edge_image_desc& d, int64_t
     return d.offset_words <= arena_words - span;
 }
 
-// Work plan (the batch workspace): int64 words [0] total units, [1] skipped
-// descriptors, [2] kPlanMagic ^ n, [3] persistent workgroups the plan was
-// made for, [4..7] reserved, [8 + i] first unit of image i (i = 0..n;
-// [8 + n] = total); then int32 first_image[b] for each persistent workgroup
-// b: the image holding that workgroup's first unit. The device planner or
-// the host planner (edge_batch_plan) writes it.
+// Work plan (the batch workspace), int64 words:
+//   [0] total units, [1] skipped descriptors, [2] kPlanMagic ^ n,
+//   [3] persistent wavefronts the plan was made for (nw), [4..7] reserved;
+//   [8 ...] n + 1 image records (PlanImage, 6 words each; record n holds
+//   only the total, as the first unit past the last image);
+//   then nw + 1 int64 first units of the wavefronts (wavefront w starts at
+//   floor(total * w / nw); entry nw = total);
+//   then nw int32 images holding each wavefront's first unit.
+// Either planner writes it: the device planner (k_plan) or the host planner
+// (edge_batch_plan). The batch kernel reads only the plan, never the table.
 constexpr int kWsHeader = 8;
 constexpr int64_t kPlanMagic = 0x45444745504c414ell;   // "EDGEPLAN"
-constexpr int kMaxBatchBlocks = 65536;
+constexpr int kMaxBatchWaves = 65536;
 constexpr int kPlanThreads = 1024;
 
-__host__ __device__ constexpr int64_t ws_block_map_offset(int32_t n) { return kWsHeader + (int64_t)n + 1; }
-// Workspace bytes for n descriptors (the block map sized for the largest grid).
+// One image of the plan: its geometry in 32-bit words and how it is cut
+// into units, so that the batch kernel does no division or re-validation
+// of the descriptor beyond one bounds test.
+struct PlanImage {
+    int64_t first;      // first unit of the image
+    int64_t off32;      // first word of the image (32-bit words from the arena start)
+    int64_t stride32;   // row pitch (32-bit words)
+    int32_t height, width;
+    int32_t wd32;       // 32-bit words per row
+    int32_t band;       // rows per unit
+    int32_t split;      // strips: 64*vw-word chunks per row; narrow units: rows per step
+    uint32_t kind;      // bits 0-2: strip words per lane (1, 2, 4), 0 for narrow
+                        // units, 7 for an image without work; bits 8-31
+                        // (narrow units): ceil(2^16 / wd32), so that
+                        // lane / wd32 = (lane * that) >> 16 for lanes < 64
+};
+static_assert(sizeof(PlanImage) == 48, "six int64 words per image record");
+constexpr int kPlanRecWords = sizeof(PlanImage) / 8;
+constexpr uint32_t kKindIdle = 7;
+
+__host__ __device__ constexpr int64_t ws_wave_first_offset(int32_t n) {
+    return kWsHeader + (int64_t)(n + 1) * kPlanRecWords;
+}
+__host__ __device__ constexpr int64_t ws_wave_image_offset(int32_t n, int64_t nw) {
+    return ws_wave_first_offset(n) + nw + 1;
+}
+// Bytes of the plan for n images and nw wavefronts; the workspace holds the
+// plan of the largest grid.
+__host__ __device__ constexpr int64_t ws_plan_bytes(int32_t n, int64_t nw) {
+    return ws_wave_image_offset(n, nw) * 8 + nw * 4;
+}
 __host__ __device__ constexpr int64_t ws_bytes(int32_t n) {
-    return ws_block_map_offset(n) * 8 + (int64_t)kMaxBatchBlocks * 4;
+    return ws_plan_bytes(n, kMaxBatchWaves);
+}
+
+// Record of descriptor d (kind kKindIdle when it has no work); returns its
+// units. *bad is set when the descriptor fails the checks of desc_ok.
+__host__ __device__ inline int64_t plan_image(const edge_image_desc& d, int64_t arena_words,
+                                              int word_bits, int vmax, int rows, PlanImage* r,
+                                              int* bad) {
+    *r = PlanImage{0, 0, 0, 0, 0, 0, 1, 1, kKindIdle};
+    if (!desc_ok(d, arena_words, word_bits)) {
+        *bad = 1;
+        return 0;
+    }
+    if (d.height == 0 || d.width == 0) return 0;
+    const int per = word_bits / 32;
+    const int shift = word_bits == 64 ? 6 : 5;
+    const int64_t wd32 = (((int64_t)d.width + word_bits - 1) >> shift) * per;
+    const UnitShape s = unit_shape(d.height, d.width, wd32, d.offset_words * per,
+                                   d.stride_words * per, vmax, rows);
+    r->off32 = d.offset_words * per;
+    r->stride32 = d.stride_words * per;
+    r->height = d.height;
+    r->width = d.width;
+    r->wd32 = (int32_t)wd32;
+    r->band = (int32_t)s.band;
+    if (s.narrow) {
+        r->split = kWave / (int)wd32;
+        r->kind = (uint32_t)((65536 + wd32 - 1) / wd32) << 8;
+    } else {
+        r->split = (int32_t)s.chunks;
+        r->kind = (uint32_t)s.vw;
+    }
+    return s.count;
 }
 
 // Units of descriptor d (0 when it fails the checks; *bad counts those).
@@ -104,29 +169,28 @@ __device__ __forceinline__ int64_t desc_units(const edge_image_desc& d, int64_t 
 // Batch planner: one workgroup; thread t owns the contiguous images
 // [t*per, (t+1)*per). It counts their work units (the first kKeep counts
 // stay in registers), one workgroup scan turns the chunk sums into each
-// image's first unit, and each thread then records, for the persistent
-// workgroups whose first unit falls inside its chunk, which image holds it
-// (workgroup b's first unit is floor(total * b / nblocks)).
+// image's first unit, each thread writes its images' records, and then the
+// wavefront map for the wavefronts whose first unit falls inside its chunk
+// (wavefront w's first unit is floor(total * w / nw)).
 constexpr int kKeep = 8;
 
 __global__ void __launch_bounds__(kPlanThreads) k_plan(const edge_image_desc* tab, int n,
                                                        int64_t arena_words, int word_bits,
-                                                       int vmax, int rows, int nblocks,
-                                                       int64_t* ws) {
+                                                       int vmax, int rows, int nw, int64_t* ws) {
     __shared__ int64_t wave_sum[kPlanThreads / kWave];
     __shared__ int bad_count;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int per = (n + kPlanThreads - 1) / kPlanThreads;
     const int i0 = min(n, tid * per), i1 = min(n, i0 + per);
-    int64_t* start = ws + kWsHeader;
-    int32_t* block_image = reinterpret_cast<int32_t*>(ws + ws_block_map_offset(n));
+    PlanImage* rec = reinterpret_cast<PlanImage*>(ws + kWsHeader);
+    int64_t* wfirst = ws + ws_wave_first_offset(n);
+    int32_t* wimg = reinterpret_cast<int32_t*>(ws + ws_wave_image_offset(n, nw));
     if (n == 0) {               // nothing to plan (a graph may be captured with n = 0)
         if (tid == 0) {
             ws[0] = 0;
             ws[1] = 0;
             ws[2] = kPlanMagic;
-            ws[3] = nblocks;
-            start[0] = 0;
+            ws[3] = nw;
         }
         return;
     }
@@ -173,131 +237,183 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan(const edge_image_desc* ta
     int64_t u = u_first;
 #pragma unroll
     for (int k = 0; k < kKeep; ++k) {
-        if (i0 + k < i1) start[i0 + k] = u;
+        if (i0 + k < i1) {
+            PlanImage r;
+            plan_image(dd[k], arena_words, word_bits, vmax, rows, &r, &unused);
+            r.first = u;
+            rec[i0 + k] = r;
+        }
         u += cnt[k];
     }
     for (int i = i0 + kKeep; i < i1; ++i) {
-        start[i] = u;
-        u += desc_units(tab[i], arena_words, word_bits, vmax, rows, &unused);
+        PlanImage r;
+        const int64_t c = plan_image(tab[i], arena_words, word_bits, vmax, rows, &r, &unused);
+        r.first = u;
+        rec[i] = r;
+        u += c;
     }
 
-    if (mine > 0) {
-        // workgroups b with floor(total*b/nblocks) in [u_first, u_first + mine)
-        const int64_t b_lo = (u_first * nblocks + total - 1) / total;
-        const int64_t b_hi = min((int64_t)nblocks, ((u_first + mine) * nblocks + total - 1) / total);
+    if (total == 0) {                                  // no work: every wavefront empty
+        for (int w = tid; w <= nw; w += kPlanThreads) {
+            wfirst[w] = 0;
+            if (w < nw) wimg[w] = 0;
+        }
+    } else if (mine > 0) {
+        // wavefronts w with floor(total*w/nw) in [u_first, u_first + mine)
+        const int64_t w_lo = (u_first * nw + total - 1) / total;
+        const int64_t w_hi = min((int64_t)nw, ((u_first + mine) * nw + total - 1) / total);
         int i = i0;
         int64_t s_i = u_first;                            // first unit of image i
-        for (int64_t b = b_lo; b < b_hi; ++b) {
-            const int64_t ub = total * b / nblocks;
+        for (int64_t w = w_lo; w < w_hi; ++w) {
+            const int64_t uw = total * w / nw;
             for (;;) {
                 const int k = i - i0;
                 int64_t c = 0;
 #pragma unroll
                 for (int q = 0; q < kKeep; ++q) c = (q == k) ? cnt[q] : c;
                 if (k >= kKeep) c = desc_units(tab[i], arena_words, word_bits, vmax, rows, &unused);
-                if (ub < s_i + c) break;
+                if (uw < s_i + c) break;
                 s_i += c;
                 ++i;
             }
-            block_image[b] = i;
+            wfirst[w] = uw;
+            wimg[w] = i;
         }
     }
     if (tid == 0) {
-        start[n] = total;
+        PlanImage end{total, 0, 0, 0, 0, 0, 1, 1, kKindIdle};
+        rec[n] = end;
+        wfirst[nw] = total;
         ws[0] = total;
         ws[1] = bad_count;     // every atomicAdd precedes the scan's barrier
         ws[2] = kPlanMagic ^ n;
-        ws[3] = nblocks;
+        ws[3] = nw;
     }
 }
 
-// Persistent batch kernel: wavefront gw of nw processes the contiguous unit
-// range [total*gw/nw, total*(gw+1)/nw) across the images of the table; its
-// first image comes from its workgroup's entry of the planner's map.
-//
-// The plan is checked before use (magic, image count, workgroup count,
-// total = last prefix), and every unit is re-checked against its image
-// (descriptor inside the arena, unit index inside the image), so a plan
-// that does not belong to this table yields wrong output, never an access
-// outside the arenas.
+// Accepts a plan record only if every word it makes the kernel touch lies
+// inside the arena and its unit shape fits the kernel's paths, whatever
+// the record holds (a plan written for another table gives wrong output,
+// never an access outside the arena).
+__device__ __forceinline__ bool record_ok(const PlanImage& r, int64_t arena32, int vmax) {
+    const uint32_t vw = r.kind & 7u;
+    if (vw == kKindIdle || r.height < 1 || r.height > kMaxHeight || r.width < 1 || r.wd32 < 1 ||
+        r.band < 1 || r.split < 1 || r.off32 < 0 || r.stride32 < r.wd32 ||
+        r.stride32 > (1ll << 32))
+        return false;
+    // (height - 1) * stride32 + wd32 < 2^30 * 2^32 + 2^31: no overflow
+    if ((int64_t)(r.height - 1) * r.stride32 + r.wd32 > arena32 - r.off32) return false;
+    if (vw == 0) return r.wd32 <= kNarrowMaxWords && r.split * r.wd32 <= kWave;
+    return r.wd32 > kNarrowMaxWords && (vw == 1 || vw == 2 || vw == 4) && (int)vw <= vmax &&
+           ((r.off32 | r.stride32) & (vw - 1)) == 0;
+}
+
+// Persistent batch kernel body: wavefront gw of nw processes the contiguous unit
+// range [wfirst[gw], wfirst[gw + 1]) across the images of the plan, starting
+// at image wimg[gw]. The header and the wavefront's map entries are loaded
+// together, then the records of its images; a unit is then a strip or a
+// group of narrow rows of one image, located by one division (none for
+// images one chunk wide).
 // VMAX: the widest strip vector width compiled in. VMAX = 1 leaves out the
 // wide strip paths, whose registers would otherwise limit how many
 // wavefronts of small crops a compute unit keeps in flight.
 template <int MODE, int VMAX>
-__global__ void __launch_bounds__(512) k_batch(const uint32_t* in, uint32_t* out,
-                                               const edge_image_desc* tab, int n,
-                                               int64_t arena_words, int word_bits,
-                                               const int64_t* ws, int vmax, int rows, uint32_t bw,
-                                               int invert) {
-    const int wpb = blockDim.x / kWave;
+__device__ __forceinline__ void batch_body(const uint32_t* in, uint32_t* out, int n,
+                                           int64_t arena32, const int64_t* ws, int vmax,
+                                           uint32_t bw, int invert, int wpb) {
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t nw = (int64_t)gridDim.x * wpb;
     const int64_t gw = (int64_t)lb * wpb + wave_uniform(threadIdx.x / kWave);
-    const int64_t total = ws[0];
-    const int64_t* start = ws + kWsHeader;
-    if (n <= 0 || ws[2] != (kPlanMagic ^ n) || ws[3] != (int64_t)gridDim.x || total < 0 ||
-        start[n] != total)
-        return;
-    const int64_t u0 = total * gw / nw;
-    const int64_t u1 = total * (gw + 1) / nw;
-    if (u0 >= u1) return;
-    int i = reinterpret_cast<const int32_t*>(ws + ws_block_map_offset(n))[lb];
-    i = i < 0 ? 0 : (i >= n ? n - 1 : i);
-    const int per = word_bits / 32;
-    // Geometry of image `cur`, computed once for all of its units in this
-    // range; `first` and `next` are the first units of images i and i + 1.
-    constexpr int64_t kNone = INT64_MAX;
+    // Every load of the header and of this wavefront's map entries first
+    // (all inside the workspace: n >= 0 and nw <= kMaxBatchWaves are checked
+    // on the host), then one combined test, so that the loads are in flight
+    // together rather than one after another behind early exits.
+    const int64_t* wfirst = ws + ws_wave_first_offset(n);
+    const int32_t* wimg = reinterpret_cast<const int32_t*>(ws + ws_wave_image_offset(n, nw));
+    const int64_t total = ws[0], magic = ws[2], plan_nw = ws[3];
+    const int64_t u0 = wfirst[gw], u1 = wfirst[gw + 1];
+    int i = wimg[gw];
+    const bool bad = (n <= 0) | (magic != (kPlanMagic ^ n)) | (plan_nw != nw) | (u0 < 0) |
+                     (u0 >= u1) | (u1 > total) | (i < 0) | (i >= n);
+    if (bad) return;
+    const PlanImage* rec = reinterpret_cast<const PlanImage*>(ws + kWsHeader);
+    PlanImage r = rec[i];                    // loaded together with the next image's first unit
+    int64_t next = rec[i + 1].first;
     int cur = -1;
     bool ok = false;
     Geom g;
-    UnitShape s{0, 1, 1, 1, 0};
-    int64_t first = start[i];
-    int64_t next = i + 1 < n ? start[i + 1] : kNone;
+    g.plane = 0;
+    g.grey = nullptr;
+    g.grey_stride = 0;
+    g.thr = 0;
+    int band = 1, split = 1, vw = 1;
+    uint32_t qmagic = 0;
     for (int64_t u = u0; u < u1; ++u) {
         while (next <= u) {
-            ++i;
-            first = next;
-            next = i + 1 < n ? start[i + 1] : kNone;
+            if (++i >= n) return;
+            r = rec[i];
+            next = rec[i + 1].first;
         }
         if (i != cur) {
             cur = i;
-            const edge_image_desc d = tab[i];
-            ok = desc_ok(d, arena_words, word_bits) && d.height > 0 && d.width > 0;
+            ok = record_ok(r, arena32, vmax);
             if (ok) {
-                const int64_t wd = ((int64_t)d.width + word_bits - 1) / word_bits * per;
-                g.in = in + d.offset_words * per;
-                g.out = out + d.offset_words * per;
-                g.stride = d.stride_words * per;
-                g.height = d.height;
-                g.width = d.width;
-                g.wd = (int32_t)wd;
-                g.plane = 0;
-                g.grey = nullptr;
-                g.grey_stride = 0;
-                g.thr = 0;
-                s = unit_shape(d.height, d.width, wd, d.offset_words * per, d.stride_words * per,
-                               vmax, rows);
+                g.in = in + r.off32;
+                g.out = out + r.off32;
+                g.stride = r.stride32;
+                g.height = r.height;
+                g.width = r.width;
+                g.wd = r.wd32;
+                band = r.band;
+                split = r.split;
+                vw = (int)(r.kind & 7u);
+                qmagic = r.kind >> 8;
             }
         }
         if (!ok) continue;
-        const int64_t local = u - first;
-        if (local < 0 || local >= s.count) continue;
-        const int64_t strip = s.chunks == 1 ? local : local / s.chunks;
-        const int64_t chunk = local - strip * s.chunks;
-        const int64_t y0 = strip * s.band;
-        const int64_t y1 = y0 + s.band < g.height ? y0 + s.band : g.height;
-        if (s.narrow) {
-            narrow_unit<MODE>(g, (int)y0, (int)y1, bw, invert != 0);
-        } else if (VMAX >= 4 && s.vw == 4) {
-            strip_unit<(VMAX >= 4 ? 4 : 1), MODE>(g, (int)(chunk * kWave * 4), (int)y0, (int)y1,
-                                                  bw, invert != 0);
-        } else if (VMAX >= 2 && s.vw == 2) {
-            strip_unit<(VMAX >= 2 ? 2 : 1), MODE>(g, (int)(chunk * kWave * 2), (int)y0, (int)y1,
-                                                  bw, invert != 0);
+        const int64_t local = u - r.first;
+        if (local < 0 || local >= (1ll << 31)) continue;
+        if (vw == 0) {
+            const int64_t y0 = local * band;
+            if (y0 >= g.height) continue;
+            const int64_t y1 = y0 + band < g.height ? y0 + band : g.height;
+            // lane layout per unit (a few VALU operations): kept across
+            // units it would hold registers through the strip paths too
+            narrow_rows<MODE>(g, narrow_lanes_q(g, split, qmagic, bw), (int)y0, (int)y1, bw,
+                              invert != 0);
+            continue;
+        }
+        const uint32_t strip = split == 1 ? (uint32_t)local : (uint32_t)local / (uint32_t)split;
+        const uint32_t chunk = (uint32_t)local - strip * (uint32_t)split;
+        const int64_t y0 = (int64_t)strip * band;
+        const int64_t j0 = (int64_t)chunk * kWave * vw;
+        if (y0 >= g.height || j0 >= g.wd) continue;
+        const int64_t y1 = y0 + band < g.height ? y0 + band : g.height;
+        if (VMAX >= 4 && vw == 4) {
+            strip_unit<(VMAX >= 4 ? 4 : 1), MODE>(g, (int)j0, (int)y0, (int)y1, bw, invert != 0);
+        } else if (VMAX >= 2 && vw == 2) {
+            strip_unit<(VMAX >= 2 ? 2 : 1), MODE>(g, (int)j0, (int)y0, (int)y1, bw, invert != 0);
         } else {
-            strip_unit<1, MODE>(g, (int)(chunk * kWave), (int)y0, (int)y1, bw, invert != 0);
+            strip_unit<1, MODE>(g, (int)j0, (int)y0, (int)y1, bw, invert != 0);
         }
     }
+}
+
+// The batch kernels: one word per lane only (the shape for small crops,
+// few enough registers for eight wavefronts per SIMD), and with the wide
+// strip paths.
+template <int MODE>
+__global__ void __launch_bounds__(512) k_batch_narrow(const uint32_t* in, uint32_t* out, int n,
+                                                         int64_t arena32, const int64_t* ws,
+                                                         int vmax, uint32_t bw, int invert, int wpb) {
+    batch_body<MODE, 1>(in, out, n, arena32, ws, vmax, bw, invert, wpb);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(512) k_batch_wide(const uint32_t* in, uint32_t* out, int n,
+                                                    int64_t arena32, const int64_t* ws, int vmax,
+                                                    uint32_t bw, int invert, int wpb) {
+    batch_body<MODE, 4>(in, out, n, arena32, ws, vmax, bw, invert, wpb);
 }
 
 // The paper's method as separate whole-image passes (sections 3-5), each a
@@ -318,7 +434,7 @@ template <int STAGE>
 __global__ void __launch_bounds__(256) k_stage(const uint32_t* img, const uint32_t* src,
                                                uint32_t* dst, int64_t stride, int32_t height,
                                                int32_t width, int32_t wd, uint32_t bw) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;    // launched with 256 threads
     if (t >= (int64_t)height * wd) return;
     const int64_t y = t / wd;
     const int j = (int)(t - y * wd);
@@ -346,17 +462,17 @@ __global__ void __launch_bounds__(256) k_stage(const uint32_t* img, const uint32
 
 // Plain 128-bit copy: the bandwidth reference.
 __global__ void __launch_bounds__(256) k_copy(const u32x4* in, u32x4* out, int64_t n16) {
-    constexpr int kPer = 4;
-    const int64_t base = (int64_t)blockIdx.x * blockDim.x * kPer + threadIdx.x;
+    constexpr int kPer = 4, kThreads = 256;                          // launched with 256 threads
+    const int64_t base = (int64_t)blockIdx.x * kThreads * kPer + threadIdx.x;
     u32x4 v[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-        const int64_t i = base + (int64_t)k * blockDim.x;
+        const int64_t i = base + (int64_t)k * kThreads;
         if (i < n16) v[k] = __builtin_nontemporal_load(in + i);
     }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-        const int64_t i = base + (int64_t)k * blockDim.x;
+        const int64_t i = base + (int64_t)k * kThreads;
         if (i < n16) __builtin_nontemporal_store(v[k], out + i);
     }
 }
@@ -419,15 +535,18 @@ int launch_strip(const Geom& g, int vw, int64_t chunks, const edge_launch_cfg& c
     switch (vw) {
         case 4:
             hipLaunchKernelGGL((k_strip<4, MODE, Pol>), dim3((uint32_t)blocks), dim3(threads), 0,
-                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert);
+                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert,
+                               c.waves_per_block);
             break;
         case 2:
             hipLaunchKernelGGL((k_strip<2, MODE, Pol>), dim3((uint32_t)blocks), dim3(threads), 0,
-                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert);
+                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert,
+                               c.waves_per_block);
             break;
         default:
             hipLaunchKernelGGL((k_strip<1, MODE, Pol>), dim3((uint32_t)blocks), dim3(threads), 0,
-                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert);
+                               stream, g, chunks, c.rows_per_tile, nunits, bw, invert,
+                               c.waves_per_block);
             break;
     }
     return launch_status();
@@ -443,7 +562,7 @@ int launch_single(const Geom& g, int vw, const edge_launch_cfg& c, uint32_t bw, 
         const int64_t blocks = ceil_div(nunits, c.waves_per_block);
         if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
         hipLaunchKernelGGL(k_narrow<MODE>, dim3((uint32_t)blocks), dim3(threads), 0, stream, g,
-                           band, nunits, bw, invert);
+                           band, nunits, bw, invert, c.waves_per_block);
         return launch_status();
     }
     const int64_t chunks = ceil_div(g.wd, (int64_t)kWave * vw);
@@ -571,16 +690,15 @@ template <int MODE>
 int launch_batch_kernel(const BatchArgs& a, int vmax, int blocks, hipStream_t s) {
     const uint32_t bw = border_word(a.border);
     const int inv = (a.flags & EDGE_FLAG_INVERT_OUT) ? 1 : 0;
+    const int64_t arena32 = a.arena_words * (a.word_bits / 32);
     if (vmax == 1)
-        hipLaunchKernelGGL((k_batch<MODE, 1>), dim3(blocks), dim3(a.cfg.waves_per_block * kWave), 0,
-                           s, (const uint32_t*)a.in, (uint32_t*)a.out, a.table, a.n,
-                           a.arena_words, a.word_bits, (const int64_t*)a.ws, vmax,
-                           a.cfg.rows_per_tile, bw, inv);
+        hipLaunchKernelGGL((k_batch_narrow<MODE>), dim3(blocks), dim3(a.cfg.waves_per_block * kWave), 0,
+                           s, (const uint32_t*)a.in, (uint32_t*)a.out, a.n, arena32,
+                           (const int64_t*)a.ws, vmax, bw, inv, a.cfg.waves_per_block);
     else
-        hipLaunchKernelGGL((k_batch<MODE, 4>), dim3(blocks), dim3(a.cfg.waves_per_block * kWave), 0,
-                           s, (const uint32_t*)a.in, (uint32_t*)a.out, a.table, a.n,
-                           a.arena_words, a.word_bits, (const int64_t*)a.ws, vmax,
-                           a.cfg.rows_per_tile, bw, inv);
+        hipLaunchKernelGGL((k_batch_wide<MODE>), dim3(blocks), dim3(a.cfg.waves_per_block * kWave), 0,
+                           s, (const uint32_t*)a.in, (uint32_t*)a.out, a.n, arena32,
+                           (const int64_t*)a.ws, vmax, bw, inv, a.cfg.waves_per_block);
     return launch_status();
 }
 
@@ -594,7 +712,7 @@ int batch_shape(const void* in, const void* out, const edge_launch_cfg& cfg, int
     v = std::min(v, alignment_words((uintptr_t)in));
     v = std::min(v, alignment_words((uintptr_t)out));
     *vmax = v;
-    *blocks = std::min(cfg.blocks_per_cu * cus, kMaxBatchBlocks);
+    *blocks = std::min(cfg.blocks_per_cu * cus, kMaxBatchWaves / cfg.waves_per_block);
     return EDGE_OK;
 }
 
@@ -604,8 +722,8 @@ int batch_enqueue(const BatchArgs& a, hipStream_t s) {
     if (rc) return rc;
     if (!(a.flags & EDGE_FLAG_PLANNED)) {
         hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, a.table, a.n,
-                           a.arena_words, a.word_bits, vmax, a.cfg.rows_per_tile, blocks,
-                           (int64_t*)a.ws);
+                           a.arena_words, a.word_bits, vmax, a.cfg.rows_per_tile,
+                           blocks * a.cfg.waves_per_block, (int64_t*)a.ws);
         rc = launch_status();
         if (rc) return rc;
     }
@@ -631,8 +749,8 @@ struct EdgeGraph {
 }  // namespace
 
 constexpr int64_t kNoAllocBytes = ws_bytes(EDGE_BATCH_NOALLOC_MAX_IMAGES);
-static_assert(kNoAllocBytes % 8 == 0 && kNoAllocBytes <= (1 << 20),
-              "a modest fixed workspace: at most 1 MiB per GPU");
+static_assert(kNoAllocBytes % 8 == 0 && kNoAllocBytes <= (2 << 20),
+              "a modest fixed workspace: at most 2 MiB per GPU");
 static __device__ __align__(256) int64_t g_noalloc_ws[kNoAllocBytes / 8];
 
 namespace {
@@ -996,34 +1114,36 @@ int edge_batch_plan(const void* in_arena, const void* out_arena, int64_t arena_w
     int vmax = 1, blocks = 1;
     rc = batch_shape(in_arena, out_arena, c, &vmax, &blocks);
     if (rc) return rc;
+    const int64_t nw = (int64_t)blocks * c.waves_per_block;
     int64_t* ws = (int64_t*)plan_host;
-    int64_t* start = ws + kWsHeader;
-    int32_t* block_image = (int32_t*)(ws + ws_block_map_offset(n_images));
-    const int per = word_bits / 32;
+    PlanImage* rec = (PlanImage*)(ws + kWsHeader);
     int64_t total = 0;
     for (int32_t i = 0; i < n_images; ++i) {
-        const edge_image_desc& d = table_host[i];
-        start[i] = total;
-        const int64_t wd = ((int64_t)d.width + word_bits - 1) / word_bits * per;
-        total += unit_shape(d.height, d.width, wd, d.offset_words * per, d.stride_words * per,
-                            vmax, c.rows_per_tile).count;
+        PlanImage r;
+        int bad = 0;
+        const int64_t units = plan_image(table_host[i], arena_words, word_bits, vmax,
+                                         c.rows_per_tile, &r, &bad);
+        r.first = total;
+        rec[i] = r;
+        total += units;
     }
-    start[n_images] = total;
+    rec[n_images] = PlanImage{total, 0, 0, 0, 0, 0, 1, 1, kKindIdle};
     for (int k = 0; k < kWsHeader; ++k) ws[k] = 0;
     ws[0] = total;
     ws[2] = kPlanMagic ^ n_images;
-    ws[3] = blocks;
+    ws[3] = nw;
+    int64_t* wfirst = ws + ws_wave_first_offset(n_images);
+    int32_t* wimg = (int32_t*)(ws + ws_wave_image_offset(n_images, nw));
     int32_t i = 0;
-    for (int b = 0; b < blocks; ++b) {
-        if (total == 0) {
-            block_image[b] = 0;
-            continue;
-        }
-        const int64_t ub = total * b / blocks;
-        while (i + 1 < n_images && start[i + 1] <= ub) ++i;
-        block_image[b] = i;
+    for (int64_t w = 0; w < nw; ++w) {
+        const int64_t uw = total * w / nw;
+        // the last image starting at or before uw: the one holding it
+        while (i + 1 < n_images && rec[i + 1].first <= uw) ++i;
+        wfirst[w] = uw;
+        wimg[w] = i;
     }
-    *plan_used_bytes = (ws_block_map_offset(n_images) * 8) + (int64_t)blocks * 4;
+    wfirst[nw] = total;
+    *plan_used_bytes = ws_plan_bytes(n_images, nw);
     return EDGE_OK;
 }
 

@@ -14,8 +14,7 @@ using namespace edgek;
 // one wavefront per strip, L levels.
 template <int L, bool EDGEOUT, class Pol>
 __global__ void __launch_bounds__(512) k_peel(Geom g, int64_t chunks, int rows, int64_t nunits,
-                                              uint32_t bw) {
-    const int wpb = blockDim.x / kWave;
+                                              uint32_t bw, int wpb) {
     const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
                          wave_uniform(threadIdx.x / kWave);
     if (unit >= nunits) return;
@@ -30,8 +29,7 @@ __global__ void __launch_bounds__(512) k_peel(Geom g, int64_t chunks, int rows, 
 // words, one wavefront per strip, L levels.
 template <int L, bool EDGEOUT, int VW>
 __global__ void __launch_bounds__(512) k_peel_vec(Geom g, int64_t chunks, int rows,
-                                                  int64_t nunits, uint32_t bw) {
-    const int wpb = blockDim.x / kWave;
+                                                  int64_t nunits, uint32_t bw, int wpb) {
     const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
                          wave_uniform(threadIdx.x / kWave);
     if (unit >= nunits) return;
@@ -70,7 +68,7 @@ int launch_peel_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t bw, hip
     if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
     hipLaunchKernelGGL((k_peel<L, EDGEOUT, CachedStrip>), dim3((uint32_t)blocks),
                        dim3(c.waves_per_block * kWave), 0, s, g, chunks, c.rows_per_tile, nunits,
-                       bw);
+                       bw, c.waves_per_block);
     return launch_status();
 }
 
@@ -82,7 +80,7 @@ int launch_peel_vec_kernel(const Geom& g, const edge_launch_cfg& c, uint32_t bw,
     if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
     hipLaunchKernelGGL((k_peel_vec<L, EDGEOUT, VW>), dim3((uint32_t)blocks),
                        dim3(c.waves_per_block * kWave), 0, s, g, chunks, c.rows_per_tile, nunits,
-                       bw);
+                       bw, c.waves_per_block);
     return launch_status();
 }
 

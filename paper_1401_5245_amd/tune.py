@@ -190,8 +190,8 @@ def tune_image(inp, out, height, width, *, mode="masks", border="white", candida
 def batch_candidates():
     # vec 1 builds the batch kernel without its wide strip paths (fewer
     # registers, more wavefronts per compute unit): best for small crops
-    for vec, rows, waves, bpc in itertools.product((1, 4), (2, 4, 8, 16), (1, 2, 4),
-                                                   (4, 8, 16, 24, 32)):
+    for vec, rows, waves, bpc in itertools.product((1, 4), (1, 2, 4, 8, 16), (1, 2, 4, 8),
+                                                   (4, 8, 12, 16, 24, 32)):
         yield dict(vec_words=vec, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=bpc,
                    cache_policy=1)
 
@@ -276,6 +276,8 @@ def _main(argv=None):
     ap.add_argument("--squares", default="",
                     help="comma-separated sides of square uint64 plain-method images to tune "
                          "instead of the default workloads (no batch)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="tune only the batch of 4096 glyph crops")
     a = ap.parse_args(argv)
     cache = TuneCache(a.out)
     rng = np.random.default_rng(a.seed)
@@ -283,6 +285,8 @@ def _main(argv=None):
               (16384, 16384, 64, "full"), (65536, 65536, 64, "masks"))
     if a.squares:
         shapes = tuple((int(v), int(v), 64, "masks") for v in a.squares.split(","))
+    if a.batch_only:
+        shapes = ()
     for (H, W, wb, mode) in shapes:
         words = -(-W // wb) * (wb // 32) * H
         inp = torch.from_numpy(rng.integers(0, 2**31, size=words, dtype=np.int64)

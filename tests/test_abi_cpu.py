@@ -146,7 +146,8 @@ def test_batch_check():
 
 def test_batch_validation():
     need = lib.edge_batch_workspace_bytes(4)
-    assert need == (8 + 5) * 8 + 65536 * 4
+    # header, 5 image records of 48 bytes, the wavefront map of the largest grid
+    assert need == (8 + 5 * 6 + 65537) * 8 + 65536 * 4
     assert lib.edge_batch_workspace_bytes(-1) < 0
     W = 0x30000000
 
