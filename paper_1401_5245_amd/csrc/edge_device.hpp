@@ -269,6 +269,11 @@ __device__ __forceinline__ uint32_t edge_word(uint32_t c, uint32_t n1, uint32_t 
 }
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t wave_uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 // Spread consecutive workgroups over the eight XCDs in contiguous ranges:
 // the dispatcher sends workgroup b to XCD b % 8, so logical block order
@@ -1014,7 +1019,7 @@ __device__ __forceinline__ NarrowLanes narrow_lanes_q(const Geom& g, int grp, ui
     const int lane = threadIdx.x & (kWave - 1);
     NarrowLanes l;
     l.wd = g.wd;
-    l.grp = grp;
+    l.grp = wave_uniform(grp);      // a wave-uniform loop step
     l.q = (int)(((uint32_t)lane * qmagic) >> 16);
     const int j = lane - l.q * l.wd;
     l.used = l.q < l.grp && j >= 0 && j < l.wd;
@@ -1049,6 +1054,31 @@ __device__ __forceinline__ void narrow_load(const Geom& g, const NarrowLanes& l,
     }
 }
 
+// Edge word of one lane in one step (every mode but the direction planes):
+// the loaded words of its row (c), the row above (u) and the row below (d),
+// pad bits and rows outside the image taken as the border; row yy.
+template <int MODE>
+__device__ __forceinline__ uint32_t narrow_word(const NarrowLanes& l, int yy, int height,
+                                                uint32_t c, uint32_t u, uint32_t d, uint32_t bw) {
+    const int j = l.j, wd = l.wd;
+    const uint32_t vm = l.vm, om = l.om;
+    const uint32_t cc = (c & vm) | om;
+    const uint32_t uu = yy > 0 ? ((u & vm) | om) : bw;
+    const uint32_t dd = yy + 1 < height ? ((d & vm) | om) : bw;
+    uint32_t cl = from_lower_lane(cc, bw), cr = from_upper_lane(cc, bw);
+    if (j == 0) cl = bw;
+    if (j == wd - 1) cr = bw;
+    uint32_t ul = bw, ur = bw, dl = bw, dr = bw;
+    if constexpr (MODE == kModeFull || MODE == kModeClause2) {
+        ul = from_lower_lane(uu, bw); ur = from_upper_lane(uu, bw);
+        dl = from_lower_lane(dd, bw); dr = from_upper_lane(dd, bw);
+        if (j == 0) { ul = bw; dl = bw; }
+        if (j == wd - 1) { ur = bw; dr = bw; }
+    }
+    return edge_word<MODE>(cc, east_of(uu, ur), uu, west_of(uu, ul), west_of(cc, cl),
+                           west_of(dd, dl), dd, east_of(dd, dr), east_of(cc, cr)) & vm;
+}
+
 // Edge words of the group starting at row y, from its loaded words.
 template <int MODE>
 __device__ __forceinline__ void narrow_emit(const Geom& g, const NarrowLanes& l, int yb, int y,
@@ -1061,22 +1091,15 @@ __device__ __forceinline__ void narrow_emit(const Geom& g, const NarrowLanes& l,
     for (int i = 0; i < kNarrowSteps; ++i) {
         const int yy = y + i * l.grp + l.q;
         const bool live = l.used && yy < yb;
-        const uint32_t cc = (r.c[i] & vm) | om;
-        const uint32_t uu = yy > 0 ? ((r.u[i] & vm) | om) : bw;
-        const uint32_t dd = yy + 1 < g.height ? ((r.d[i] & vm) | om) : bw;
-        uint32_t cl = from_lower_lane(cc, bw), cr = from_upper_lane(cc, bw);
-        if (j == 0) cl = bw;
-        if (j == wd - 1) cr = bw;
-        uint32_t ul = bw, ur = bw, dl = bw, dr = bw;
-        if constexpr (MODE == kModeFull || MODE == kModeClause2) {
-            ul = from_lower_lane(uu, bw); ur = from_upper_lane(uu, bw);
-            dl = from_lower_lane(dd, bw); dr = from_upper_lane(dd, bw);
-            if (j == 0) { ul = bw; dl = bw; }
-            if (j == wd - 1) { ur = bw; dr = bw; }
-        }
         uint32_t* op = row;                       // row yy of this lane
         row += step;
         if constexpr (MODE == kModeDirections) {
+            const uint32_t cc = (r.c[i] & vm) | om;
+            const uint32_t uu = yy > 0 ? ((r.u[i] & vm) | om) : bw;
+            const uint32_t dd = yy + 1 < g.height ? ((r.d[i] & vm) | om) : bw;
+            uint32_t cl = from_lower_lane(cc, bw), cr = from_upper_lane(cc, bw);
+            if (j == 0) cl = bw;
+            if (j == wd - 1) cr = bw;
             const uint32_t m = ~cc & vm;
             if (live) {
                 op[0] = m & west_of(cc, cl);
@@ -1085,10 +1108,54 @@ __device__ __forceinline__ void narrow_emit(const Geom& g, const NarrowLanes& l,
                 op[3 * g.plane] = m & dd;
             }
         } else {
-            const uint32_t v = edge_word<MODE>(cc, east_of(uu, ur), uu, west_of(uu, ul),
-                                               west_of(cc, cl), west_of(dd, dl), dd,
-                                               east_of(dd, dr), east_of(cc, cr)) & vm;
+            const uint32_t v = narrow_word<MODE>(l, yy, g.height, r.c[i], r.u[i], r.d[i], bw);
             if (live) op[0] = invert ? (v ^ vm) : v;
+        }
+    }
+}
+
+// Rows [ya, yb) by 32-bit byte offsets from one scalar base row (the row
+// above ya, or row 0), for units whose rows span less than 2^32 bytes (any
+// mode but the direction planes). A lane's word in its row is the base plus
+// its offset, clamped to the last word the unit may read (so that lanes
+// past the unit read a valid word); the rows above and below are that
+// offset minus or plus the pitch, clamped to the same range. Words so read
+// from outside the image are replaced by the border in narrow_word. No
+// 64-bit address arithmetic and no per-row selects of pointers remain.
+template <int MODE>
+__device__ __forceinline__ void narrow_rows32(const Geom& g, const NarrowLanes& l, int ya, int yb,
+                                              uint32_t bw, bool invert) {
+    const int base_row = ya > 0 ? ya - 1 : 0;
+    const int last_row = yb < g.height ? yb : g.height - 1;
+    const uint32_t pitch = (uint32_t)g.stride * 4u;
+    const char* in = reinterpret_cast<const char*>(g.in + (int64_t)base_row * g.stride);
+    char* out = reinterpret_cast<char*>(g.out + (int64_t)base_row * g.stride);
+    const uint32_t last = (uint32_t)(last_row - base_row) * pitch + (uint32_t)(l.wd - 1) * 4u;
+    const uint32_t lane0 =
+        l.used ? (uint32_t)(ya - base_row + l.q) * pitch + (uint32_t)l.j * 4u : 0u;
+    const uint32_t step = (uint32_t)l.grp * pitch;
+    for (int y = ya; y < yb; y += l.grp * kNarrowSteps) {
+        const uint32_t o0 = (uint32_t)(y - ya) * pitch;
+        uint32_t oc[kNarrowSteps], c[kNarrowSteps], u[kNarrowSteps], d[kNarrowSteps];
+#pragma unroll
+        for (int i = 0; i < kNarrowSteps; ++i) {
+            oc[i] = min(lane0 + (o0 + (uint32_t)i * step), last);
+            const uint32_t ou = max(oc[i], pitch) - pitch;
+            const uint32_t od = min(oc[i] + pitch, last);
+            c[i] = *reinterpret_cast<const uint32_t*>(in + oc[i]);
+            u[i] = *reinterpret_cast<const uint32_t*>(in + ou);
+            d[i] = *reinterpret_cast<const uint32_t*>(in + od);
+        }
+#pragma unroll
+        for (int i = 0; i < kNarrowSteps; ++i) {
+            const int yy = y + i * l.grp + l.q;
+            uint32_t v = narrow_word<MODE>(l, yy, g.height, c[i], u[i], d[i], bw);
+            v = invert ? (v ^ l.vm) : v;
+            // formed in every lane before the store's branch: left to the
+            // compiler, the word (and the loads of its rows above and
+            // below) sink into the branch, a second round trip per group
+            asm volatile("" : "+v"(v));
+            if (l.used && yy < yb) *reinterpret_cast<uint32_t*>(out + oc[i]) = v;
         }
     }
 }
@@ -1096,6 +1163,12 @@ __device__ __forceinline__ void narrow_emit(const Geom& g, const NarrowLanes& l,
 template <int MODE>
 __device__ __forceinline__ void narrow_rows(const Geom& g, const NarrowLanes& l, int ya, int yb,
                                             uint32_t bw, bool invert) {
+    if constexpr (MODE != kModeDirections) {
+        if ((int64_t)(yb - ya + 2) * g.stride * 4 < (int64_t(1) << 32)) {
+            narrow_rows32<MODE>(g, l, ya, yb, bw, invert);
+            return;
+        }
+    }
     for (int y = ya; y < yb; y += l.grp * kNarrowSteps) {
         NarrowGroup r;
         narrow_load(g, l, ya, yb, y, r);

@@ -358,14 +358,17 @@ __device__ __forceinline__ void batch_body(const uint32_t* in, uint32_t* out, in
             cur = i;
             ok = record_ok(r, arena32, vmax);
             if (ok) {
-                g.in = in + r.off32;
-                g.out = out + r.off32;
-                g.stride = r.stride32;
-                g.height = r.height;
-                g.width = r.width;
-                g.wd = r.wd32;
-                band = r.band;
-                split = r.split;
+                // wave-uniform by construction; stated, so that the
+                // geometry stays in scalar registers through the unit loops
+                const int64_t off = wave_uniform64(r.off32);
+                g.in = in + off;
+                g.out = out + off;
+                g.stride = wave_uniform64(r.stride32);
+                g.height = wave_uniform(r.height);
+                g.width = wave_uniform(r.width);
+                g.wd = wave_uniform(r.wd32);
+                band = wave_uniform(r.band);
+                split = wave_uniform(r.split);
                 vw = (int)(r.kind & 7u);
                 qmagic = r.kind >> 8;
             }
