@@ -283,7 +283,7 @@ int edge_batch(const void* in_arena, void* out_arena, int64_t arena_words,
  * capture, tight serving loops, harnesses that forbid hipMalloc): edge_batch
  * with the workspace held by the library. The work plan goes into a fixed
  * device array in the library's code object, 256-byte aligned, one per GPU
- * (about 1.5 MiB each, held until the process ends), sized for at most
+ * (about 5.3 MiB each, held until the process ends), sized for at most
  * EDGE_BATCH_NOALLOC_MAX_IMAGES images; its device address is looked up
  * once per GPU, on the first call with that GPU current.
  *   Arguments as edge_batch, without the workspace. The current device must

@@ -75,9 +75,11 @@ __host__ __device__ static inline bool desc_ok(const edge_image_desc& d, int64_t
 //   [3] persistent wavefronts the plan was made for (nw), [4..7] reserved;
 //   [8 ...] n + 1 image records (PlanImage, 6 words each; record n holds
 //   only the total, as the first unit past the last image);
-//   then nw + 1 int64 first units of the wavefronts (wavefront w starts at
-//   floor(total * w / nw); entry nw = total);
-//   then nw int32 images holding each wavefront's first unit.
+//   then nw + 1 wavefront entries (PlanWave, 9 words each): wavefront w
+//   starts at unit floor(total * w / nw), and its entry also holds the
+//   image of that unit, the first unit of the next image and a copy of the
+//   image's record, so that a wavefront reaches its first unit's geometry
+//   with the loads of the header (entry nw: first unit = total).
 // Either planner writes it: the device planner (k_plan) or the host planner
 // (edge_batch_plan). The batch kernel reads only the plan, never the table.
 constexpr int kWsHeader = 8;
@@ -105,16 +107,23 @@ static_assert(sizeof(PlanImage) == 48, "six int64 words per image record");
 constexpr int kPlanRecWords = sizeof(PlanImage) / 8;
 constexpr uint32_t kKindIdle = 7;
 
-__host__ __device__ constexpr int64_t ws_wave_first_offset(int32_t n) {
+struct PlanWave {
+    int64_t first;      // first unit of the wavefront
+    int64_t next;       // first unit of the image after `image`
+    int32_t image;      // image holding unit `first`
+    int32_t reserved;
+    PlanImage rec;      // that image's record
+};
+static_assert(sizeof(PlanWave) == 72, "nine int64 words per wavefront entry");
+constexpr int kPlanWaveWords = sizeof(PlanWave) / 8;
+
+__host__ __device__ constexpr int64_t ws_wave_offset(int32_t n) {
     return kWsHeader + (int64_t)(n + 1) * kPlanRecWords;
-}
-__host__ __device__ constexpr int64_t ws_wave_image_offset(int32_t n, int64_t nw) {
-    return ws_wave_first_offset(n) + nw + 1;
 }
 // Bytes of the plan for n images and nw wavefronts; the workspace holds the
 // plan of the largest grid.
 __host__ __device__ constexpr int64_t ws_plan_bytes(int32_t n, int64_t nw) {
-    return ws_wave_image_offset(n, nw) * 8 + nw * 4;
+    return (ws_wave_offset(n) + (nw + 1) * kPlanWaveWords) * 8;
 }
 __host__ __device__ constexpr int64_t ws_bytes(int32_t n) {
     return ws_plan_bytes(n, kMaxBatchWaves);
@@ -183,8 +192,7 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan(const edge_image_desc* ta
     const int per = (n + kPlanThreads - 1) / kPlanThreads;
     const int i0 = min(n, tid * per), i1 = min(n, i0 + per);
     PlanImage* rec = reinterpret_cast<PlanImage*>(ws + kWsHeader);
-    int64_t* wfirst = ws + ws_wave_first_offset(n);
-    int32_t* wimg = reinterpret_cast<int32_t*>(ws + ws_wave_image_offset(n, nw));
+    PlanWave* wv = reinterpret_cast<PlanWave*>(ws + ws_wave_offset(n));
     if (n == 0) {               // nothing to plan (a graph may be captured with n = 0)
         if (tid == 0) {
             ws[0] = 0;
@@ -253,11 +261,9 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan(const edge_image_desc* ta
         u += c;
     }
 
+    const PlanImage idle{0, 0, 0, 0, 0, 0, 1, 1, kKindIdle};
     if (total == 0) {                                  // no work: every wavefront empty
-        for (int w = tid; w <= nw; w += kPlanThreads) {
-            wfirst[w] = 0;
-            if (w < nw) wimg[w] = 0;
-        }
+        for (int w = tid; w <= nw; w += kPlanThreads) wv[w] = PlanWave{0, 0, 0, 0, idle};
     } else if (mine > 0) {
         // wavefronts w with floor(total*w/nw) in [u_first, u_first + mine)
         const int64_t w_lo = (u_first * nw + total - 1) / total;
@@ -266,9 +272,10 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan(const edge_image_desc* ta
         int64_t s_i = u_first;                            // first unit of image i
         for (int64_t w = w_lo; w < w_hi; ++w) {
             const int64_t uw = total * w / nw;
+            int64_t c;                                     // units of image i
             for (;;) {
                 const int k = i - i0;
-                int64_t c = 0;
+                c = 0;
 #pragma unroll
                 for (int q = 0; q < kKeep; ++q) c = (q == k) ? cnt[q] : c;
                 if (k >= kKeep) c = desc_units(tab[i], arena_words, word_bits, vmax, rows, &unused);
@@ -276,14 +283,22 @@ __global__ void __launch_bounds__(kPlanThreads) k_plan(const edge_image_desc* ta
                 s_i += c;
                 ++i;
             }
-            wfirst[w] = uw;
-            wimg[w] = i;
+            // image i's record was written above by this same thread; copied
+            // word by word (a whole record in registers spills here)
+            wv[w].first = uw;
+            wv[w].next = s_i + c;
+            wv[w].image = i;
+            wv[w].reserved = 0;
+            const int64_t* src = reinterpret_cast<const int64_t*>(rec + i);
+            int64_t* dst = reinterpret_cast<int64_t*>(&wv[w].rec);
+            for (int k = 0; k < kPlanRecWords; ++k) dst[k] = src[k];
         }
     }
     if (tid == 0) {
-        PlanImage end{total, 0, 0, 0, 0, 0, 1, 1, kKindIdle};
+        PlanImage end = idle;
+        end.first = total;
         rec[n] = end;
-        wfirst[nw] = total;
+        wv[nw] = PlanWave{total, total, n, 0, end};
         ws[0] = total;
         ws[1] = bad_count;     // every atomicAdd precedes the scan's barrier
         ws[2] = kPlanMagic ^ n;
@@ -309,36 +324,41 @@ __device__ __forceinline__ bool record_ok(const PlanImage& r, int64_t arena32, i
 }
 
 // Persistent batch kernel body: wavefront gw of nw processes the contiguous unit
-// range [wfirst[gw], wfirst[gw + 1]) across the images of the plan, starting
-// at image wimg[gw]. The header and the wavefront's map entries are loaded
-// together, then the records of its images; a unit is then a strip or a
-// group of narrow rows of one image, located by one division (none for
-// images one chunk wide).
+// range [first of entry gw, first of entry gw + 1) across the images of the
+// plan, starting with the image and record its entry holds. The header and
+// the two entries are loaded together; records of later images are loaded
+// when the range reaches them. A unit is a strip or a group of narrow rows
+// of one image, located by one division (none for images one chunk wide).
 // VMAX: the widest strip vector width compiled in. VMAX = 1 leaves out the
 // wide strip paths, whose registers would otherwise limit how many
 // wavefronts of small crops a compute unit keeps in flight.
 template <int MODE, int VMAX>
 __device__ __forceinline__ void batch_body(const uint32_t* in, uint32_t* out, int n,
                                            int64_t arena32, const int64_t* ws, int vmax,
-                                           uint32_t bw, int invert, int wpb) {
-    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t nw = (int64_t)gridDim.x * wpb;
+                                           uint32_t bw, int invert, int wpb, uint32_t nblocks) {
+    const uint32_t lb = xcd_block(blockIdx.x, nblocks);
+    const int64_t nw = (int64_t)nblocks * wpb;
     const int64_t gw = (int64_t)lb * wpb + wave_uniform(threadIdx.x / kWave);
     // Every load of the header and of this wavefront's map entries first
     // (all inside the workspace: n >= 0 and nw <= kMaxBatchWaves are checked
     // on the host), then one combined test, so that the loads are in flight
     // together rather than one after another behind early exits.
-    const int64_t* wfirst = ws + ws_wave_first_offset(n);
-    const int32_t* wimg = reinterpret_cast<const int32_t*>(ws + ws_wave_image_offset(n, nw));
+    const PlanWave* wv = reinterpret_cast<const PlanWave*>(ws + ws_wave_offset(n));
     const int64_t total = ws[0], magic = ws[2], plan_nw = ws[3];
-    const int64_t u0 = wfirst[gw], u1 = wfirst[gw + 1];
-    int i = wimg[gw];
+    const int64_t u0 = wv[gw].first, u1 = wv[gw + 1].first;
+    int64_t next = wv[gw].next;
+    int i = wv[gw].image;
+    PlanImage r = wv[gw].rec;
+    // the entry's fields count as used here (no instruction results), so
+    // that their loads are issued with the header's; left alone, the
+    // compiler sinks them below the exit test, one more round trip
+    asm volatile("" ::"s"(next), "s"(r.first), "s"(r.off32), "s"(r.stride32), "s"(r.height),
+                 "s"(r.width), "s"(r.wd32), "s"(r.band), "s"(r.split), "s"(r.kind), "s"(in),
+                 "s"(out));
     const bool bad = (n <= 0) | (magic != (kPlanMagic ^ n)) | (plan_nw != nw) | (u0 < 0) |
                      (u0 >= u1) | (u1 > total) | (i < 0) | (i >= n);
     if (bad) return;
     const PlanImage* rec = reinterpret_cast<const PlanImage*>(ws + kWsHeader);
-    PlanImage r = rec[i];                    // loaded together with the next image's first unit
-    int64_t next = rec[i + 1].first;
     int cur = -1;
     bool ok = false;
     Geom g;
@@ -404,19 +424,22 @@ __device__ __forceinline__ void batch_body(const uint32_t* in, uint32_t* out, in
 
 // The batch kernels: one word per lane only (the shape for small crops,
 // few enough registers for eight wavefronts per SIMD), and with the wide
-// strip paths.
+// strip paths. The grid's workgroup count and size come in as arguments
+// (no argument beyond the explicit ones is read).
 template <int MODE>
 __global__ void __launch_bounds__(512) k_batch_narrow(const uint32_t* in, uint32_t* out, int n,
                                                          int64_t arena32, const int64_t* ws,
-                                                         int vmax, uint32_t bw, int invert, int wpb) {
-    batch_body<MODE, 1>(in, out, n, arena32, ws, vmax, bw, invert, wpb);
+                                                         int vmax, uint32_t bw, int invert, int wpb,
+                                                         uint32_t nblocks) {
+    batch_body<MODE, 1>(in, out, n, arena32, ws, vmax, bw, invert, wpb, nblocks);
 }
 
 template <int MODE>
 __global__ void __launch_bounds__(512) k_batch_wide(const uint32_t* in, uint32_t* out, int n,
                                                     int64_t arena32, const int64_t* ws, int vmax,
-                                                    uint32_t bw, int invert, int wpb) {
-    batch_body<MODE, 4>(in, out, n, arena32, ws, vmax, bw, invert, wpb);
+                                                    uint32_t bw, int invert, int wpb,
+                                                    uint32_t nblocks) {
+    batch_body<MODE, 4>(in, out, n, arena32, ws, vmax, bw, invert, wpb, nblocks);
 }
 
 // The paper's method as separate whole-image passes (sections 3-5), each a
@@ -697,11 +720,13 @@ int launch_batch_kernel(const BatchArgs& a, int vmax, int blocks, hipStream_t s)
     if (vmax == 1)
         hipLaunchKernelGGL((k_batch_narrow<MODE>), dim3(blocks), dim3(a.cfg.waves_per_block * kWave), 0,
                            s, (const uint32_t*)a.in, (uint32_t*)a.out, a.n, arena32,
-                           (const int64_t*)a.ws, vmax, bw, inv, a.cfg.waves_per_block);
+                           (const int64_t*)a.ws, vmax, bw, inv, a.cfg.waves_per_block,
+                           (uint32_t)blocks);
     else
         hipLaunchKernelGGL((k_batch_wide<MODE>), dim3(blocks), dim3(a.cfg.waves_per_block * kWave), 0,
                            s, (const uint32_t*)a.in, (uint32_t*)a.out, a.n, arena32,
-                           (const int64_t*)a.ws, vmax, bw, inv, a.cfg.waves_per_block);
+                           (const int64_t*)a.ws, vmax, bw, inv, a.cfg.waves_per_block,
+                           (uint32_t)blocks);
     return launch_status();
 }
 
@@ -752,8 +777,8 @@ struct EdgeGraph {
 }  // namespace
 
 constexpr int64_t kNoAllocBytes = ws_bytes(EDGE_BATCH_NOALLOC_MAX_IMAGES);
-static_assert(kNoAllocBytes % 8 == 0 && kNoAllocBytes <= (2 << 20),
-              "a modest fixed workspace: at most 2 MiB per GPU");
+static_assert(kNoAllocBytes % 8 == 0 && kNoAllocBytes <= (8 << 20),
+              "a modest fixed workspace: at most 8 MiB per GPU");
 static __device__ __align__(256) int64_t g_noalloc_ws[kNoAllocBytes / 8];
 
 namespace {
@@ -1135,17 +1160,15 @@ int edge_batch_plan(const void* in_arena, const void* out_arena, int64_t arena_w
     ws[0] = total;
     ws[2] = kPlanMagic ^ n_images;
     ws[3] = nw;
-    int64_t* wfirst = ws + ws_wave_first_offset(n_images);
-    int32_t* wimg = (int32_t*)(ws + ws_wave_image_offset(n_images, nw));
+    PlanWave* wv = (PlanWave*)(ws + ws_wave_offset(n_images));
     int32_t i = 0;
     for (int64_t w = 0; w < nw; ++w) {
         const int64_t uw = total * w / nw;
         // the last image starting at or before uw: the one holding it
         while (i + 1 < n_images && rec[i + 1].first <= uw) ++i;
-        wfirst[w] = uw;
-        wimg[w] = i;
+        wv[w] = PlanWave{uw, i < n_images ? rec[i + 1].first : total, i, 0, rec[i]};
     }
-    wfirst[nw] = total;
+    wv[nw] = PlanWave{total, total, n_images, 0, rec[n_images]};
     *plan_used_bytes = ws_plan_bytes(n_images, nw);
     return EDGE_OK;
 }

@@ -146,8 +146,9 @@ def test_batch_check():
 
 def test_batch_validation():
     need = lib.edge_batch_workspace_bytes(4)
-    # header, 5 image records of 48 bytes, the wavefront map of the largest grid
-    assert need == (8 + 5 * 6 + 65537) * 8 + 65536 * 4
+    # header, 5 image records of 48 bytes, 65537 wavefront entries of 72 bytes
+    # (the largest grid)
+    assert need == (8 + 5 * 6 + 65537 * 9) * 8
     assert lib.edge_batch_workspace_bytes(-1) < 0
     W = 0x30000000
 
