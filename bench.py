@@ -1136,6 +1136,13 @@ def cpu_baseline(img, seconds):
 
 # Sections whose results are summarised in the final line (and written in
 # full to the detail file), in the order they run.
+def headline_section(torch, em, tm, args) -> dict:
+    """The headline workload on its own (for profiling runs)."""
+    res = headline_full(torch, em, args)
+    res.pop("img")
+    return res
+
+
 SUMMARY_SECTIONS = {
     "plain_512": lambda torch, em, tm, a: plain_512(torch, em, tm, 2000),
     "plain_8192": lambda torch, em, tm, a: plain_8192(torch, em, tm),
@@ -1155,6 +1162,7 @@ DETAIL_SECTIONS = {
     "cpu_configs": lambda torch, em, tm, a: cpu_oracle_configs(None),
 }
 SECTIONS = dict(SUMMARY_SECTIONS, **DETAIL_SECTIONS, **{
+    "full_16384": headline_section,
     # the plain copy of 8, 64 or 512 MiB: the reference reading that scales
     # hardware counters of the edge kernels in the same profiled run
     "copy_8MiB": lambda torch, em, tm, a: round(copy_ceiling(torch, em, tm, 8 << 20, 40, 40), 1),

@@ -735,6 +735,10 @@ __device__ __forceinline__ void peel_unit(const Geom& g, int64_t chunk, int y0, 
 // the barrier does not pay anyway.
 constexpr int kPeelVecLevels = 7;
 constexpr int kPeelVecBarrierLevels = 3;
+// The cause of the wrong four-level words was never shown; until it is, the
+// barrier stays out of every instantiation from four levels up.
+static_assert(kPeelVecBarrierLevels < 4,
+              "four or more levels with the loop-body barrier gave wrong words at -O3");
 
 template <int L, bool EDGEOUT, int VW, bool WHOLE, class Pol>
 __device__ __forceinline__ void peel_vec_unit(const Geom& g, int j0, int y0, int y1,
