@@ -502,6 +502,18 @@ def full_65536(torch, em, tm, steps=10):
                     "sampled_rows_bit_exact": ok and (ok2 if mode == "full" else True)}
     res["full_vs_plain_time"] = round(res["full"]["ms_per_launch"] / res["plain"]["ms_per_launch"],
                                       4)
+    # The full-mode kernel compiles to the plain kernel's instructions (the
+    # compiler finds the second clause absorbed by the first); the clause-2
+    # diagnostic evaluates the bit-sliced count in full, so its time is what
+    # evaluating clause 2 costs on this image.
+    for _ in range(3):
+        em.edge_full(inp, out, H, W, clause2_only=True)
+    ms2 = float(np.median([tm.per_call_ms(lambda i: em.edge_full(inp, out, H, W,
+                                                                 clause2_only=True), steps)
+                           for _ in range(3)]))
+    res["clause2"] = {"ms_per_launch": round(ms2, 4), "roofline": roofline(nbytes, ms2),
+                      "sampled_rows_bit_exact": ok2}
+    res["clause2_vs_plain_time"] = round(ms2 / res["plain"]["ms_per_launch"], 4)
     del inp, out
     torch.cuda.empty_cache()
     return res
@@ -1221,6 +1233,7 @@ def summarise(detail: dict) -> dict:
     if d:
         out["full_65536_u64"] = {"gpx_s": d["full"]["gpx_s"], "frac": d["full"]["roofline"]["frac"],
                                  "vs_plain_time": d["full_vs_plain_time"],
+                                 "clause2_vs_plain_time": d.get("clause2_vs_plain_time"),
                                  "exact": d["full"]["sampled_rows_bit_exact"]}
     d = detail.get("batched_4096")
     if d:
