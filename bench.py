@@ -357,7 +357,8 @@ def plain_8192(torch, em, tm, steps=4000, stream_counts=(1, 2, 4)):
                         f"{steps} launches",
             "launch_cfg": cfg or "built-in",
             "us_per_launch": round(ms * 1e3, 3), "gpx_s": round(H * W / (ms * 1e-3) / 1e9, 1),
-            "roofline": roofline(nbytes, ms), "bit_exact": exact and replay_ok,
+            "roofline": roofline(nbytes, ms, measured_traffic("k_strip_plain_8192x8192_u64.md")),
+            "bit_exact": exact and replay_ok,
             "trials_us": [round(t * 1e3, 3) for t in trials],
             "graph_streams_us_per_launch": {str(k): round(v * 1e3, 3)
                                             for k, v in per_streams.items()},
