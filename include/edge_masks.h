@@ -69,7 +69,7 @@
 extern "C" {
 #endif
 
-#define EDGE_MASKS_ABI_VERSION 1
+#define EDGE_MASKS_ABI_VERSION 2
 
 /* Largest image height (rows) any entry point accepts. */
 #define EDGE_MAX_HEIGHT (1 << 30)
@@ -115,22 +115,39 @@ typedef struct edge_image_desc {
 
 /* Launch configuration (NULL selects the built-in choice).
  *   vec_words       32-bit words per lane for wide rows: 1, 2 or 4.
- *   rows_per_tile   rows one wavefront walks down per work unit, 1..1024.
+ *   rows_per_tile   rows one wavefront walks down per work unit, 1..1024
+ *                   (1..EDGE_TILE_MAX_ROWS with EDGE_SHAPE_TILE).
  *   waves_per_block wavefronts per workgroup: 1, 2, 4 or 8.
  *   blocks_per_cu   persistent workgroups per compute unit (batch only),
  *                   1..32; ignored by the single-image calls.
  *   cache_policy    EDGE_CACHE_AUTO (by image size), EDGE_CACHE_NORMAL or
  *                   EDGE_CACHE_STREAM (non-temporal loads and stores);
- *                   single images only, batches use EDGE_CACHE_NORMAL. */
+ *                   single images only, batches use EDGE_CACHE_NORMAL.
+ *   shape           how a single image's rows of more than 32 words are
+ *                   cut into work: EDGE_SHAPE_STRIP (a wavefront walks its
+ *                   rows with a few rows in flight), EDGE_SHAPE_TILE (a
+ *                   wavefront requests all rows of its unit at once, always
+ *                   with non-temporal loads and stores; cache_policy is not
+ *                   used; workgroups in dispatch order) or
+ *                   EDGE_SHAPE_TILE_XCD (the same tiles, workgroups
+ *                   regrouped so that each XCD takes a contiguous part of
+ *                   the image, as strips always are). Ignored by batches,
+ *                   by rows of at most 32 words and by the grey-input and
+ *                   peeling calls. */
 typedef struct edge_launch_cfg {
     int32_t vec_words;
     int32_t rows_per_tile;
     int32_t waves_per_block;
     int32_t blocks_per_cu;
     int32_t cache_policy;
+    int32_t shape;
 } edge_launch_cfg;
 
 enum { EDGE_CACHE_AUTO = 0, EDGE_CACHE_NORMAL = 1, EDGE_CACHE_STREAM = 2 };
+enum { EDGE_SHAPE_STRIP = 0, EDGE_SHAPE_TILE = 1, EDGE_SHAPE_TILE_XCD = 2 };
+
+/* Most rows of one EDGE_SHAPE_TILE work unit. */
+#define EDGE_TILE_MAX_ROWS 16
 
 /* Plain method (Boolean function Edge(p), section 1; stages of sections
  * 3-5). `in`, `out`: device pointers to height rows of stride_words words.

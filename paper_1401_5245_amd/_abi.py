@@ -42,11 +42,15 @@ class EdgeImageDesc(ctypes.Structure):
 EDGE_CACHE_AUTO = 0
 EDGE_CACHE_NORMAL = 1
 EDGE_CACHE_STREAM = 2
+EDGE_SHAPE_STRIP = 0
+EDGE_SHAPE_TILE = 1
+EDGE_SHAPE_TILE_XCD = 2
+EDGE_TILE_MAX_ROWS = 16
 
 
 class EdgeLaunchCfg(ctypes.Structure):
     _fields_ = [("vec_words", c_i32), ("rows_per_tile", c_i32), ("waves_per_block", c_i32),
-                ("blocks_per_cu", c_i32), ("cache_policy", c_i32)]
+                ("blocks_per_cu", c_i32), ("cache_policy", c_i32), ("shape", c_i32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -54,7 +58,8 @@ class EdgeLaunchCfg(ctypes.Structure):
     @classmethod
     def from_dict(cls, d: dict) -> "EdgeLaunchCfg":
         return cls(int(d["vec_words"]), int(d["rows_per_tile"]), int(d["waves_per_block"]),
-                   int(d.get("blocks_per_cu", 1)), int(d.get("cache_policy", EDGE_CACHE_AUTO)))
+                   int(d.get("blocks_per_cu", 1)), int(d.get("cache_policy", EDGE_CACHE_AUTO)),
+                   int(d.get("shape", EDGE_SHAPE_STRIP)))
 
 
 class EdgeError(RuntimeError):
@@ -109,7 +114,7 @@ _SIGNATURES = {
     "edge_abi_version": (ctypes.c_int, []),
 }
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 _lib = None
 
 

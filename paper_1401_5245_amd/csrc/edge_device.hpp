@@ -51,18 +51,30 @@ constexpr int kNarrowMaxWords = 32;
 enum { kModePlain = 0, kModeFull = 1, kModeClause2 = 2, kModeDirections = 3, kModePeel = 4,
        kModeCopy = 5 };
 
-// Compile-time choices of the strip loop: rows kept in flight per lane, and
-// non-temporal (streaming) cache policy for the row loads and stores.
-template <int PREFETCH, bool NT_LOAD, bool NT_STORE>
+// Compile-time choices of the strip loop: rows kept in flight per lane,
+// non-temporal (streaming) cache policy for the row loads and stores, and
+// ONESHOT: the unit's rows are all requested at the start and the ring is
+// never refilled, so a unit holds at most PREFETCH rows.
+template <int PREFETCH, bool NT_LOAD, bool NT_STORE, bool ONESHOT = false>
 struct StripPolicy {
     static constexpr int prefetch = PREFETCH;
     static constexpr bool nt_load = NT_LOAD;
     static constexpr bool nt_store = NT_STORE;
+    static constexpr bool oneshot = ONESHOT;
 };
 // Images that fit in the caches keep normal loads and stores (halo rows and
 // the output stay cached for the next consumer); large images stream.
 using CachedStrip = StripPolicy<4, false, false>;
 using StreamingStrip = StripPolicy<4, true, true>;
+// Tiles: a wavefront requests all rows of its tile and the two halo rows
+// at once, computes the rows as they arrive and ends. Short-lived
+// wavefronts with their whole input in flight keep the memory system's
+// queues fuller than long strips walking a few rows ahead. Tiles keep the
+// dispatcher's workgroup order (no regrouping by XCD): the workgroups in
+// flight then form one window sweeping down the image.
+constexpr int kTileMaxRows = 16;
+template <int R>
+using TileStrip = StripPolicy<R, true, true, true>;
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -332,6 +344,9 @@ __device__ __forceinline__ void store_words(uint32_t* p, const uint32_t (&w)[VW]
 //
 // Each lane keeps Pol::prefetch rows in flight in the ring q[]: the slot of
 // the row just consumed is refilled with the row that many rows further down.
+// With Pol::oneshot the unit is a tile of at most Pol::prefetch rows
+// (y1 - y0 <= Pol::prefetch, kept by the caller) whose rows are all loaded
+// before the first is used.
 // Loads never branch: rows past y1 re-read row y1 (an L1 hit) and rows
 // outside the image are clamped into it and replaced by the border after
 // the load, so the hardware's in-order load counter waits exactly for the
@@ -440,6 +455,27 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
         }
     };
 
+    if constexpr (Pol::oneshot) {
+        // every row of the tile and its two halo rows requested at once
+        // (rows past y1 re-read row y1); then each row as it arrives
+        Raw t[P + 2];
+#pragma unroll
+        for (int i = 0; i < P + 2; ++i) t[i] = load_raw(min(y0 - 1 + i, y1));
+        __builtin_amdgcn_sched_barrier(0);
+        Row up = shift_row(t[0], y0 - 1);
+        Row cur = shift_row(t[1], y0);
+#pragma unroll
+        for (int o = 0; o < P; ++o) {
+            const int y = y0 + o;
+            if (y < y1) {
+                const Row dn = shift_row(t[o + 2], y + 1);
+                emit(y, up, cur, dn);
+                up = cur;
+                cur = dn;
+            }
+        }
+        return;
+    }
     const Raw ra = load_raw(y0 - 1);
     const Raw rb = load_raw(y0);
     Raw q[P];

@@ -56,7 +56,10 @@ inline bool cfg_ok(const edge_launch_cfg& c) {
            (c.waves_per_block == 1 || c.waves_per_block == 2 || c.waves_per_block == 4 ||
             c.waves_per_block == 8) &&
            c.blocks_per_cu >= 1 && c.blocks_per_cu <= 32 && c.cache_policy >= EDGE_CACHE_AUTO &&
-           c.cache_policy <= EDGE_CACHE_STREAM;
+           c.cache_policy <= EDGE_CACHE_STREAM &&
+           (c.shape == EDGE_SHAPE_STRIP ||
+            ((c.shape == EDGE_SHAPE_TILE || c.shape == EDGE_SHAPE_TILE_XCD) &&
+             c.rows_per_tile <= EDGE_TILE_MAX_ROWS));
 }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -18,18 +18,23 @@
 using namespace edgek;
 using namespace edgeh;
 
+static_assert(kTileMaxRows == EDGE_TILE_MAX_ROWS, "tile height of the kernels and the ABI");
+
 static_assert(kMaxHeight == EDGE_MAX_HEIGHT, "one height limit for the header and the kernels");
 
 // ================================================================ kernels ===
 
-// One image, strips of `rows` rows x 64*VW words, one wavefront per strip.
-// wpb: wavefronts per workgroup, passed in (reading the workgroup size
-// costs every wavefront a dependent load before its first unit).
+// One image, strips of `rows` rows x 64*VW words, one wavefront per strip
+// (for a tile policy, rows <= its height). by_xcd: workgroups regrouped by
+// XCD, so that vertically adjacent strips share one L2 (always for strips);
+// else the dispatch order. wpb: wavefronts per workgroup, passed in
+// (reading the workgroup size costs every wavefront a dependent load
+// before its first unit).
 template <int VW, int MODE, class Pol>
 __global__ void __launch_bounds__(512) k_strip(Geom g, int64_t chunks, int rows, int64_t nunits,
-                                               uint32_t bw, int invert, int wpb) {
-    const int64_t unit = (int64_t)xcd_block(blockIdx.x, gridDim.x) * wpb +
-                         wave_uniform(threadIdx.x / kWave);
+                                               uint32_t bw, int invert, int wpb, int by_xcd) {
+    const uint32_t b = by_xcd ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int64_t unit = (int64_t)b * wpb + wave_uniform(threadIdx.x / kWave);
     if (unit >= nunits) return;
     const int64_t strip = unit / chunks;
     const int64_t chunk = unit - strip * chunks;
@@ -514,12 +519,14 @@ using namespace edgeh;
 // steps. Wider rows: four words per lane when the row fills at least 75% of
 // its 256-word spans, else two (a half-used 4-word span loses to twice the
 // wavefronts: 3.1 against 4.4 us at 4096^2, 5.2 against 7.1 us at 6000^2).
-// Images of up to 16 MiB of traffic are bound by launch latency and take
-// 2-row strips (the most wavefronts); larger ones take about 1024 strips
-// (at most 256 rows each), so that every wavefront walks far enough to
-// amortise its halo rows.
+// Images of under 3 MiB of traffic are bound by launch latency and take
+// 2-row strips (the most wavefronts); larger ones take tiles in dispatch
+// order, 4 wavefronts per workgroup, of 4 rows up to 12 MiB, 8 rows up to
+// 64 MiB and 16 rows from there (uint64 squares, full definition, against
+// the strips this replaces: 4096^2 2.99 / 3.15 us, 8192^2 4.58 / 5.43,
+// 16384^2 13.48 / 14.23, 32768^2 49.1 / 50.0, 65536^2 189.4 / 192.6).
 edge_launch_cfg default_single(int64_t height, int64_t wd32) {
-    edge_launch_cfg c;
+    edge_launch_cfg c{};
     c.blocks_per_cu = 1;
     c.cache_policy = EDGE_CACHE_AUTO;
     if (wd32 <= kNarrowMaxWords) {
@@ -530,12 +537,29 @@ edge_launch_cfg default_single(int64_t height, int64_t wd32) {
     } else {
         const int64_t span4 = (int64_t)kWave * 4;
         c.vec_words = 4 * wd32 >= 3 * span4 * ceil_div(wd32, span4) ? 4 : 2;
-        const int v = pick_vw(wd32, c.vec_words, 0, 0);
-        const int64_t chunks = ceil_div(wd32, (int64_t)kWave * v);
-        const bool small = 2 * height * wd32 * 4 <= (16ll << 20);
-        c.rows_per_tile = small ? 2 : (int32_t)pow2_floor(std::max<int64_t>(2, std::min<int64_t>(256, chunks * height / 1024)));
-        c.waves_per_block = c.rows_per_tile >= 256 ? 8 : 4;
+        const int64_t traffic = 2 * height * wd32 * 4;
+        c.waves_per_block = 4;
+        if (traffic < (3ll << 20)) {
+            c.rows_per_tile = 2;
+        } else {
+            c.shape = EDGE_SHAPE_TILE;
+            c.rows_per_tile = traffic < (12ll << 20) ? 4 : traffic < (64ll << 20) ? 8 : 16;
+        }
     }
+    return c;
+}
+
+// Strips only (four fundamental-edge planes, single peels): about 1024
+// strips of at most 256 rows above 16 MiB of traffic, else 2-row strips.
+edge_launch_cfg default_strips(int64_t height, int64_t wd32) {
+    edge_launch_cfg c = default_single(height, wd32);
+    if (wd32 <= kNarrowMaxWords) return c;
+    const int v = pick_vw(wd32, c.vec_words, 0, 0);
+    const int64_t chunks = ceil_div(wd32, (int64_t)kWave * v);
+    const bool small = 2 * height * wd32 * 4 <= (16ll << 20);
+    c.shape = EDGE_SHAPE_STRIP;
+    c.rows_per_tile = small ? 2 : (int32_t)pow2_floor(std::max<int64_t>(2, std::min<int64_t>(256, chunks * height / 1024)));
+    c.waves_per_block = c.rows_per_tile >= 256 ? 8 : 4;
     return c;
 }
 
@@ -545,7 +569,7 @@ edge_launch_cfg default_single(int64_t height, int64_t wd32) {
 constexpr int64_t kStreamBytes = 4ll << 20;
 
 edge_launch_cfg default_batch() {
-    edge_launch_cfg c;
+    edge_launch_cfg c{};
     c.vec_words = 4;
     c.rows_per_tile = 8;
     c.waves_per_block = 4;
@@ -557,22 +581,23 @@ edge_launch_cfg default_batch() {
 template <int MODE, class Pol>
 int launch_strip(const Geom& g, int vw, int64_t chunks, const edge_launch_cfg& c, int64_t nunits,
                  int64_t blocks, uint32_t bw, int invert, hipStream_t stream) {
+    const int by_xcd = Pol::oneshot ? c.shape == EDGE_SHAPE_TILE_XCD : 1;
     const int threads = c.waves_per_block * kWave;
     switch (vw) {
         case 4:
             hipLaunchKernelGGL((k_strip<4, MODE, Pol>), dim3((uint32_t)blocks), dim3(threads), 0,
                                stream, g, chunks, c.rows_per_tile, nunits, bw, invert,
-                               c.waves_per_block);
+                               c.waves_per_block, by_xcd);
             break;
         case 2:
             hipLaunchKernelGGL((k_strip<2, MODE, Pol>), dim3((uint32_t)blocks), dim3(threads), 0,
                                stream, g, chunks, c.rows_per_tile, nunits, bw, invert,
-                               c.waves_per_block);
+                               c.waves_per_block, by_xcd);
             break;
         default:
             hipLaunchKernelGGL((k_strip<1, MODE, Pol>), dim3((uint32_t)blocks), dim3(threads), 0,
                                stream, g, chunks, c.rows_per_tile, nunits, bw, invert,
-                               c.waves_per_block);
+                               c.waves_per_block, by_xcd);
             break;
     }
     return launch_status();
@@ -595,6 +620,17 @@ int launch_single(const Geom& g, int vw, const edge_launch_cfg& c, uint32_t bw, 
     const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
     const int64_t blocks = ceil_div(nunits, c.waves_per_block);
     if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
+    // tiles for the edge map and its diagnostic and direction planes; the
+    // single-level peels (copy, one peel) always walk strips
+    if constexpr (MODE != kModeCopy && MODE != kModePeel) {
+        const bool tile = c.shape == EDGE_SHAPE_TILE || c.shape == EDGE_SHAPE_TILE_XCD;
+        if (tile && c.rows_per_tile <= 8)
+            return launch_strip<MODE, TileStrip<8>>(g, vw, chunks, c, nunits, blocks, bw, invert,
+                                                    stream);
+        if (tile)
+            return launch_strip<MODE, TileStrip<kTileMaxRows>>(g, vw, chunks, c, nunits, blocks,
+                                                               bw, invert, stream);
+    }
     bool stream_mode = c.cache_policy == EDGE_CACHE_STREAM;
     if (c.cache_policy == EDGE_CACHE_AUTO)
         stream_mode = 2 * (int64_t)g.height * g.wd * 4 >= kStreamBytes;
@@ -641,7 +677,8 @@ int image_launch(const void* in, void* out, int64_t height, int64_t width, int64
     g.grey = nullptr;
     g.grey_stride = 0;
     g.thr = 0;
-    edge_launch_cfg c = cfg ? *cfg : default_single(height, g.wd);
+    edge_launch_cfg c = cfg ? *cfg : planes == 4 ? default_strips(height, g.wd)
+                                                : default_single(height, g.wd);
     // four planes out per row in: 2-row strips keep more stores in flight
     // (measured at 8192^2: 9.9 us against 11.0 us with the plain shape)
     if (!cfg && planes == 4 && g.wd > kNarrowMaxWords) c.rows_per_tile = 2;
@@ -823,7 +860,7 @@ int noalloc_workspace(void** addr) {
 // against 238-264 / 295-298 us; at 16384^2 level, at 8192^2 slower), when
 // the image's alignment allows it (vec_ok), else the one-word shape.
 edge_launch_cfg default_peel(int64_t height, int64_t wd32, int levels, bool vec_ok = true) {
-    edge_launch_cfg c;
+    edge_launch_cfg c{};
     const bool large = vec_ok && levels >= 4 && levels <= kPeelVecLevels &&
                        height * wd32 * 32 >= (int64_t(1) << 30);
     c.vec_words = (vec_ok && levels <= 3) || large ? 4 : 1;
@@ -982,7 +1019,7 @@ int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int thresh
     g.grey = (const uint8_t*)grey;
     g.grey_stride = grey_stride_bytes;
     g.thr = (uint32_t)threshold;
-    edge_launch_cfg c;
+    edge_launch_cfg c{};
     if (cfg) {
         c = *cfg;
     } else {
@@ -1042,7 +1079,8 @@ int edge_peel(const void* in, void* out, int64_t height, int64_t width, int64_t 
     if (levels <= 1) {
         // One level (one peel, or the edge map of the image) or none: the
         // strip loop of the single-image kernels with that word function.
-        const edge_launch_cfg c = cfg ? *cfg : default_single(height, g.wd);
+        edge_launch_cfg c = cfg ? *cfg : default_strips(height, g.wd);
+        c.shape = EDGE_SHAPE_STRIP;
         int vmax = std::min(c.vec_words, std::min(alignment_words(pin), alignment_words(pout)));
         const int vw = pick_vw(g.wd, vmax, 0, g.stride);
         if (levels == 0) return launch_single<kModeCopy>(g, vw, c, bw, 0, s);

@@ -1,5 +1,6 @@
 """Autotuner for launch configurations (words per lane, rows per tile,
-wavefronts per workgroup, persistent workgroups per CU, cache policy).
+wavefronts per workgroup, persistent workgroups per CU, cache policy, strip
+or tile shape).
 
 Each candidate is timed on the device from a captured graph of repeated
 launches (so host launch overhead does not decide), and is admitted only
@@ -128,7 +129,15 @@ def image_candidates(height: int, width: int, word_bits: int):
         if rows > max(2, height):
             continue
         yield dict(vec_words=vec, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=1,
-                   cache_policy=cache)
+                   cache_policy=cache, shape=_abi.EDGE_SHAPE_STRIP)
+    # tiles (all rows of a unit requested at once), in dispatch order or
+    # regrouped by XCD
+    for vec, rows, waves, shape in itertools.product(
+            (2, 4), (4, 8, 16), (2, 4, 8), (_abi.EDGE_SHAPE_TILE, _abi.EDGE_SHAPE_TILE_XCD)):
+        if rows > max(4, height):
+            continue
+        yield dict(vec_words=vec, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=1,
+                   cache_policy=0, shape=shape)
 
 
 def _rotate_time_us(fns, reps: int) -> float:

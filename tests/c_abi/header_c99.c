@@ -18,7 +18,7 @@ int main(void) {
         (any_fn)edge_graph_destroy, (any_fn)edge_copy_bytes, (any_fn)edge_status_string,
         (any_fn)edge_last_hip_error, (any_fn)edge_abi_version};
     edge_image_desc d = {0, 1, 1, 1};
-    edge_launch_cfg c = {4, 8, 4, 1, EDGE_CACHE_AUTO};
+    edge_launch_cfg c = {4, 8, 4, 1, EDGE_CACHE_AUTO, EDGE_SHAPE_STRIP};
     (void)masks;
     (void)d;
     (void)c;

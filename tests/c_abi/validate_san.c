@@ -61,9 +61,12 @@ int main(void) {
     expect(edge_image_launch(A, B, 4, 100, 4, 32, 0, 0, EDGE_FLAG_CLAUSE2_ONLY, NULL, NULL),
            EDGE_ERR_INVALID, "clause 2 in plain mode");
     {
-        const edge_launch_cfg bad[] = {{3, 4, 4, 1, 0}, {4, 0, 4, 1, 0}, {4, 4, 3, 1, 0},
-                                       {4, 4, 4, 0, 0}, {4, 2000, 4, 1, 0}, {4, 4, 4, 33, 0},
-                                       {4, 4, 4, 1, 3}, {4, 4, 4, 1, -1}};
+        const edge_launch_cfg bad[] = {{3, 4, 4, 1, 0, 0},   {4, 0, 4, 1, 0, 0},
+                                       {4, 4, 3, 1, 0, 0},   {4, 4, 4, 0, 0, 0},
+                                       {4, 2000, 4, 1, 0, 0}, {4, 4, 4, 33, 0, 0},
+                                       {4, 4, 4, 1, 3, 0},   {4, 4, 4, 1, -1, 0},
+                                       {4, EDGE_TILE_MAX_ROWS + 1, 4, 1, 0, EDGE_SHAPE_TILE},
+                                       {4, 4, 4, 1, 0, 3},   {4, 4, 4, 1, 0, -1}};
         for (unsigned i = 0; i < sizeof bad / sizeof bad[0]; ++i) {
             edge_launch_cfg* c = (edge_launch_cfg*)malloc(sizeof *c);
             *c = bad[i];

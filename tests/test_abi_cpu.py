@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_version_and_strings():
-    assert lib.edge_abi_version() == 1
+    assert lib.edge_abi_version() == 2
     for s in (OK, INVALID, ALIGN, ALIAS, _abi.EDGE_ERR_HIP, WS, _abi.EDGE_ERR_UNSUPPORTED):
         assert lib.edge_status_string(s)
     assert lib.edge_status_string(-99) == b"unknown status"
@@ -76,9 +76,14 @@ def test_mode_flag_and_cfg_validation():
     assert lib.edge_full(A, B, 4, 100, 4, 32, 0, 8, None) == INVALID
     for bad in ((3, 4, 4, 1, 0), (4, 0, 4, 1, 0), (4, 4, 3, 1, 0), (4, 4, 4, 0, 0),
                 (4, 2000, 4, 1, 0), (4, 4, 16, 1, 0), (4, 4, 4, 33, 0), (4, 4, 4, 1, 3),
-                (4, 4, 4, 1, -1)):
+                (4, 4, 4, 1, -1), (4, _abi.EDGE_TILE_MAX_ROWS + 1, 4, 1, 0, _abi.EDGE_SHAPE_TILE),
+                (4, 4, 4, 1, 0, 3), (4, 4, 4, 1, 0, -1)):
         cfg = _abi.EdgeLaunchCfg(*bad)
         assert launch(cfg=ctypes.byref(cfg)) == INVALID, bad
+    # tiles up to EDGE_TILE_MAX_ROWS rows pass the checks (the launch
+    # itself is not reached: H = 0)
+    ok = _abi.EdgeLaunchCfg(4, _abi.EDGE_TILE_MAX_ROWS, 4, 1, 0, _abi.EDGE_SHAPE_TILE)
+    assert launch(cfg=ctypes.byref(ok), H=0) == OK
     # adjacent, non-overlapping buffers are fine up to the launch; exactly
     # touching ranges (out right after in) must not be reported as aliasing
     assert launch(out=A + 4 * 16, H=0) == OK
@@ -110,11 +115,17 @@ def test_default_cfg():
     assert lib.edge_default_cfg(-1, 8, 32, 0, 0, ctypes.byref(c)) == INVALID
     assert lib.edge_default_cfg(100, 100, 32, 0, 1, ctypes.byref(c)) == OK
     assert c.blocks_per_cu >= 1
-    # strip heights of the built-in shape: 2 rows up to 16 MiB of traffic,
-    # then about 1024 strips, at most 256 rows
-    for side, rows in ((2048, 2), (8192, 2), (16384, 32), (32768, 128), (65536, 256)):
+    # built-in shape of uint64 squares: 2-row strips under 3 MiB of traffic,
+    # then tiles of 4 rows (to 12 MiB), 8 rows (to 64 MiB) and 16 rows
+    for side, shape, rows in ((2048, _abi.EDGE_SHAPE_STRIP, 2), (4096, _abi.EDGE_SHAPE_TILE, 4),
+                              (8192, _abi.EDGE_SHAPE_TILE, 8), (11584, _abi.EDGE_SHAPE_TILE, 8),
+                              (16384, _abi.EDGE_SHAPE_TILE, 16), (65536, _abi.EDGE_SHAPE_TILE, 16)):
         assert lib.edge_default_cfg(side, side, 64, 0, 0, ctypes.byref(c)) == OK
-        assert c.rows_per_tile == rows, (side, c.rows_per_tile)
+        assert (c.shape, c.rows_per_tile) == (shape, rows), (side, c.shape, c.rows_per_tile)
+        assert c.rows_per_tile <= _abi.EDGE_TILE_MAX_ROWS or c.shape == _abi.EDGE_SHAPE_STRIP
+    # rows of at most 32 words: narrow units whatever the size
+    assert lib.edge_default_cfg(65536, 1024, 32, 0, 0, ctypes.byref(c)) == OK
+    assert c.vec_words == 1 and c.shape == _abi.EDGE_SHAPE_STRIP
     # four words per lane only when the rows fill 75% of their 256-word spans
     for side, vec in ((4096, 2), (6000, 2), (6200, 4), (8192, 4), (9600, 2), (12800, 4)):
         assert lib.edge_default_cfg(side, side, 64, 0, 0, ctypes.byref(c)) == OK

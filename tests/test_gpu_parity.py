@@ -79,6 +79,53 @@ def test_launch_configs(vec, rows, waves, cache):
             assert_same(got, expect(img, mode=mode, clause2_only=c2), f"{cfg} {H}x{W}")
 
 
+# Tiles: a multi-chunk row with a partial last chunk (33000 pixels), whole
+# 256-word chunks (16384 pixels of uint64), rows of one partial chunk, one
+# row, rows of at most 32 words (which take the narrow kernel whatever the
+# shape) and uint32 rows that split a 64-bit word
+TILE_IMAGES = ((70, 4100, 64), (100, 33000, 64), (17, 16384, 64), (1, 2000, 32), (5, 700, 64),
+               (33, 1000, 32), (40, 16416, 32))
+TILE_CASES = (("masks", False, "white", False), ("full", False, "black", True),
+              ("full", True, "white", False))
+_tile_expected = {}
+
+
+def _tile_case(H, W, mode, c2, border, inv):
+    key = (H, W, mode, c2, border, inv)
+    if key not in _tile_expected:
+        img = rand_img(H, W, 0.45, seed=H * 7 + W)
+        _tile_expected[key] = (img, expect(img, border=border, mode=mode, clause2_only=c2,
+                                           invert=inv))
+    return _tile_expected[key]
+
+
+@pytest.mark.parametrize("vec", [1, 2, 4])
+@pytest.mark.parametrize("rows", [1, 2, 7, 8, 9, 16])
+@pytest.mark.parametrize("waves", [1, 4, 8])
+@pytest.mark.parametrize("shape", [1, 2])
+def test_tile_configs(vec, rows, waves, shape):
+    """Tiles (every row of a unit requested at once) of every height up to
+    the most, in both workgroup orders, against the oracle."""
+    cfg = dict(vec_words=vec, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=1,
+               cache_policy=0, shape=shape)
+    for (H, W, wb) in TILE_IMAGES:
+        for (mode, c2, border, inv) in TILE_CASES:
+            img, want = _tile_case(H, W, mode, c2, border, inv)
+            _, got = run_single(img, wb, mode=mode, clause2_only=c2, border=border, invert=inv,
+                                cfg=cfg)
+            assert_same(got, want, f"{cfg} {H}x{W} B{wb} {mode} c2={c2} {border} inv={inv}")
+
+
+@pytest.mark.parametrize("H,W,wb", [(1600, 8200, 64), (1200, 12000, 32), (3300, 4100, 64)])
+def test_builtin_tiles(H, W, wb):
+    """Images of 3 MiB of traffic and more take tiles by default: whole
+    images against the oracle, in both modes, strides and pads too."""
+    img = rand_img(H, W, 0.3, seed=H + W)
+    for mode in ("masks", "full"):
+        _, got = run_single(img, wb, mode=mode, stride_extra=3 if wb == 64 else 5)
+        assert_same(got, expect(img, mode=mode), f"{H}x{W} B{wb} {mode}")
+
+
 def test_translation_every_bit_offset():
     """A fixed pattern at every x offset across two 64-bit words and several
     rows: catches carry and direction mistakes."""
