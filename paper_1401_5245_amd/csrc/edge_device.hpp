@@ -334,9 +334,12 @@ __device__ __forceinline__ void store_words(uint32_t* p, const uint32_t (&w)[VW]
 
 // Rows [y0, y1) of words [j0, j0 + 64*VW) of image g, by the calling
 // wavefront (all 64 lanes active; every branch below is wave-uniform).
-// WHOLE: the span lies inside the row, so each lane moves its VW words with
-// one vector load and store; otherwise (the row's last chunk) each word is
-// loaded from a clamped address and stored only when it is inside the row.
+// WHOLE: the span lies inside the row. Otherwise (the row's last chunk)
+// VW divides the row's word count (strip_vw), so each lane's words lie
+// either all inside the row or all past its end. Either way a lane inside
+// moves its VW words with one vector load and store; lanes past the end
+// load the chunk's first words instead (an address inside the row; their
+// words become border words) and store nothing.
 // `bw` is the border word (all ones for a white border, zero for black).
 //
 // EDGES: some word just outside the span lies inside the row, so lanes 0
@@ -359,14 +362,10 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
     const int jl = j0 + lane * VW;
 
     uint32_t vm[VW], om[VW];
-    int jw[VW];
-    bool inrow[VW];
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
         vm[k] = valid_bits(jl + k, g.width);
         om[k] = bw & ~vm[k];
-        inrow[k] = jl + k < g.wd;
-        jw[k] = inrow[k] ? jl + k : j0;
     }
 
     // Words just outside the wavefront's span: lane 0 needs the word on the
@@ -379,16 +378,13 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
     struct Raw { uint32_t w[VW]; uint32_t e; };
     struct Row { uint32_t c[VW], w[VW], e[VW]; };
 
+    const bool inside_row = WHOLE || jl < g.wd;   // the lane's VW words are in the row
+    const int jv = inside_row ? jl : j0;
     auto load_raw = [&](int y) {
         const int yc = y < 0 ? 0 : (y >= g.height ? g.height - 1 : y);
         Raw r;
         const uint32_t* rp = g.in + (int64_t)yc * g.stride;
-        if constexpr (WHOLE) {
-            load_words<VW, Pol::nt_load>(rp + jl, r.w);
-        } else {
-#pragma unroll
-            for (int k = 0; k < VW; ++k) r.w[k] = rp[jw[k]];
-        }
+        load_words<VW, Pol::nt_load>(rp + jv, r.w);
         if constexpr (EDGES) r.e = rp[je_load];
         else r.e = bw;
         return r;
@@ -415,13 +411,7 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
     };
 
     auto store_row = [&](uint32_t* op, const uint32_t (&res)[VW]) {
-        if constexpr (WHOLE) {
-            store_words<VW, Pol::nt_store>(op + jl, res);
-        } else {
-#pragma unroll
-            for (int k = 0; k < VW; ++k)
-                if (inrow[k]) op[jl + k] = res[k];
-        }
+        if (inside_row) store_words<VW, Pol::nt_store>(op + jl, res);
     };
 
     auto emit = [&](int y, const Row& up, const Row& cur, const Row& dn) {
@@ -1234,6 +1224,15 @@ __host__ __device__ inline int pick_vw(int64_t wd, int vmax, int64_t offset_word
     return v;
 }
 
+// Words per lane of the strip and tile kernels: as pick_vw, and a divisor
+// of the row's word count, so that no lane's words straddle the row's end.
+__host__ __device__ inline int strip_vw(int64_t wd, int vmax, int64_t offset_words,
+                                        int64_t stride_words) {
+    int v = pick_vw(wd, vmax, offset_words, stride_words);
+    while (v > 1 && (wd & (v - 1)) != 0) v /= 2;
+    return v;
+}
+
 // Work units of one image (0 for an empty image). All quotients fit 32 bits
 // (height < 2^31, wd < 2^26, band <= 64 * 1024), so they use 32-bit division.
 struct UnitShape {
@@ -1253,7 +1252,7 @@ __host__ __device__ inline UnitShape unit_shape(int64_t height, int64_t width, i
         s.narrow = 1;
         s.band = (uint32_t)(kWave / wd) * (uint32_t)rows;
     } else {
-        s.vw = pick_vw(wd, vmax, offset_words, stride_words);
+        s.vw = strip_vw(wd, vmax, offset_words, stride_words);
         const uint32_t span = (uint32_t)kWave * (uint32_t)s.vw;
         s.chunks = ((uint32_t)wd - 1u) / span + 1u;
         s.band = (uint32_t)rows;

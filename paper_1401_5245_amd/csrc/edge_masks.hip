@@ -325,7 +325,7 @@ __device__ __forceinline__ bool record_ok(const PlanImage& r, int64_t arena32, i
     if ((int64_t)(r.height - 1) * r.stride32 + r.wd32 > arena32 - r.off32) return false;
     if (vw == 0) return r.wd32 <= kNarrowMaxWords && r.split * r.wd32 <= kWave;
     return r.wd32 > kNarrowMaxWords && (vw == 1 || vw == 2 || vw == 4) && (int)vw <= vmax &&
-           ((r.off32 | r.stride32) & (vw - 1)) == 0;
+           ((r.off32 | r.stride32 | r.wd32) & (vw - 1)) == 0;
 }
 
 // Persistent batch kernel body: wavefront gw of nw processes the contiguous unit
@@ -554,7 +554,7 @@ edge_launch_cfg default_single(int64_t height, int64_t wd32) {
 edge_launch_cfg default_strips(int64_t height, int64_t wd32) {
     edge_launch_cfg c = default_single(height, wd32);
     if (wd32 <= kNarrowMaxWords) return c;
-    const int v = pick_vw(wd32, c.vec_words, 0, 0);
+    const int v = strip_vw(wd32, c.vec_words, 0, 0);
     const int64_t chunks = ceil_div(wd32, (int64_t)kWave * v);
     const bool small = 2 * height * wd32 * 4 <= (16ll << 20);
     c.shape = EDGE_SHAPE_STRIP;
@@ -692,7 +692,7 @@ int image_launch(const void* in, void* out, int64_t height, int64_t width, int64
     vmax = std::min(vmax, alignment_words(pin));
     vmax = std::min(vmax, alignment_words(pout));
     if (planes > 1) vmax = std::min(vmax, alignment_words((uintptr_t)(plane_words * word_bytes)));
-    const int vw = pick_vw(g.wd, vmax, 0, g.stride);
+    const int vw = strip_vw(g.wd, vmax, 0, g.stride);
     const uint32_t bw = border_word(border);
     const int inv = (flags & EDGE_FLAG_INVERT_OUT) ? 1 : 0;
     hipStream_t s = (hipStream_t)hip_stream;
@@ -1082,7 +1082,7 @@ int edge_peel(const void* in, void* out, int64_t height, int64_t width, int64_t 
         edge_launch_cfg c = cfg ? *cfg : default_strips(height, g.wd);
         c.shape = EDGE_SHAPE_STRIP;
         int vmax = std::min(c.vec_words, std::min(alignment_words(pin), alignment_words(pout)));
-        const int vw = pick_vw(g.wd, vmax, 0, g.stride);
+        const int vw = strip_vw(g.wd, vmax, 0, g.stride);
         if (levels == 0) return launch_single<kModeCopy>(g, vw, c, bw, 0, s);
         if (edge_out) return launch_single<kModePlain>(g, vw, c, bw, 0, s);
         return launch_single<kModePeel>(g, vw, c, bw, 0, s);
