@@ -116,7 +116,9 @@ typedef struct edge_image_desc {
 /* Launch configuration (NULL selects the built-in choice).
  *   vec_words       32-bit words per lane for wide rows: 1, 2 or 4.
  *   rows_per_tile   rows one wavefront walks down per work unit, 1..1024
- *                   (1..EDGE_TILE_MAX_ROWS with EDGE_SHAPE_TILE).
+ *                   (1..EDGE_TILE_MAX_ROWS for tiles; for bands, the rows
+ *                   each wavefront loads: 1, 2 or 4, with
+ *                   waves_per_block * rows_per_tile >= 3).
  *   waves_per_block wavefronts per workgroup: 1, 2, 4 or 8.
  *   blocks_per_cu   persistent workgroups per compute unit (batch only),
  *                   1..32; ignored by the single-image calls.
@@ -131,9 +133,14 @@ typedef struct edge_image_desc {
  *                   used; workgroups in dispatch order) or
  *                   EDGE_SHAPE_TILE_XCD (the same tiles, workgroups
  *                   regrouped so that each XCD takes a contiguous part of
- *                   the image, as strips always are). Ignored by batches,
- *                   by rows of at most 32 words and by the grey-input and
- *                   peeling calls. */
+ *                   the image, as strips always are), or EDGE_SHAPE_BAND /
+ *                   EDGE_SHAPE_BAND_XCD (a workgroup loads
+ *                   waves_per_block * rows_per_tile consecutive rows of one
+ *                   chunk into LDS at once and computes all but the first
+ *                   and last; non-temporal loads and stores; edge-map calls
+ *                   only: edge_directions returns EDGE_ERR_UNSUPPORTED).
+ *                   Ignored by batches, by rows of at most 32 words and by
+ *                   the grey-input and peeling calls. */
 typedef struct edge_launch_cfg {
     int32_t vec_words;
     int32_t rows_per_tile;
@@ -144,7 +151,8 @@ typedef struct edge_launch_cfg {
 } edge_launch_cfg;
 
 enum { EDGE_CACHE_AUTO = 0, EDGE_CACHE_NORMAL = 1, EDGE_CACHE_STREAM = 2 };
-enum { EDGE_SHAPE_STRIP = 0, EDGE_SHAPE_TILE = 1, EDGE_SHAPE_TILE_XCD = 2 };
+enum { EDGE_SHAPE_STRIP = 0, EDGE_SHAPE_TILE = 1, EDGE_SHAPE_TILE_XCD = 2, EDGE_SHAPE_BAND = 3,
+       EDGE_SHAPE_BAND_XCD = 4 };
 
 /* Most rows of one EDGE_SHAPE_TILE work unit. */
 #define EDGE_TILE_MAX_ROWS 16

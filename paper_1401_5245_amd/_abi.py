@@ -45,6 +45,8 @@ EDGE_CACHE_STREAM = 2
 EDGE_SHAPE_STRIP = 0
 EDGE_SHAPE_TILE = 1
 EDGE_SHAPE_TILE_XCD = 2
+EDGE_SHAPE_BAND = 3
+EDGE_SHAPE_BAND_XCD = 4
 EDGE_TILE_MAX_ROWS = 16
 
 

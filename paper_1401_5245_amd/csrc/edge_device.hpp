@@ -599,6 +599,104 @@ __device__ __forceinline__ void strip_unit(const Geom& g, int j0, int y0, int y1
     }
 }
 
+// ------------------------------------------------------------------ bands ----
+
+// Bands: a workgroup of nw wavefronts loads the nw * RW consecutive rows
+// y0 - 1 .. y0 + nw * RW - 2 of one chunk of 64 * VW words (wavefront w the
+// rows w, w + nw, ...), every row in flight at once; writes them to LDS with
+// pad bits and rows outside the image set to the border, together with the
+// word just left and the word just right of the chunk; and computes the
+// nw * RW - 2 rows between the first and the last from LDS, each wavefront a
+// contiguous share. Neighbouring bands overlap by two rows, so the halo
+// rows cost 2 / (nw * RW) of the reads. VW divides the row's word count
+// (strip_vw): a lane's words are all inside the row or all past its end.
+// An LDS row holds the left word at kBandLeft, the chunk's words from
+// kBandBody (16-byte aligned) and the right word after them.
+constexpr int kBandLeft = 3, kBandBody = 4;
+__host__ __device__ constexpr int band_pitch(int vw) { return kWave * vw + 8; }
+
+template <int VW, int RW, int MODE>
+__device__ __forceinline__ void band_unit(const Geom& g, uint32_t* lds, int nw, int j0,
+                                          int64_t y0, uint32_t bw, bool invert) {
+    constexpr int PITCH = band_pitch(VW), RIGHT = kBandBody + kWave * VW;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = wave_uniform(threadIdx.x / kWave);
+    const int jl = j0 + lane * VW;
+    const bool inside_row = jl < g.wd;
+    const int jv = inside_row ? jl : j0;
+    uint32_t vm[VW], om[VW];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+        vm[k] = valid_bits(jl + k, g.width);
+        om[k] = bw & ~vm[k];
+    }
+    const bool has_l = j0 > 0, has_r = j0 + kWave * VW < g.wd;
+    // lane 0 loads the word left of the chunk, lane 63 the word right of it
+    // (when inside the row); the other lanes load the chunk's first word
+    const int je = (lane == 0 && has_l) ? j0 - 1 : ((lane == kWave - 1 && has_r) ? j0 + kWave * VW : j0);
+    const uint32_t vme = valid_bits(j0 + kWave * VW, g.width), ome = bw & ~vme;
+
+    uint32_t q[RW][VW], e[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const int64_t y = y0 - 1 + (int64_t)i * nw + w;
+        const int64_t yc = y < 0 ? 0 : (y >= g.height ? g.height - 1 : y);
+        const uint32_t* rp = g.in + yc * g.stride;
+        load_words<VW, true>(rp + jv, q[i]);
+        e[i] = rp[je];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const int l = i * nw + w;
+        const int64_t y = y0 - 1 + l;
+        const bool inside = y >= 0 && y < g.height;
+        uint32_t v[VW];
+#pragma unroll
+        for (int k = 0; k < VW; ++k) v[k] = inside ? ((q[i][k] & vm[k]) | om[k]) : bw;
+        uint32_t* t = lds + l * PITCH;
+        store_words<VW, false>(t + kBandBody + lane * VW, v);
+        if (lane == 0) t[kBandLeft] = inside && has_l ? e[i] : bw;
+        if (lane == kWave - 1) t[RIGHT] = inside && has_r ? ((e[i] & vme) | ome) : bw;
+    }
+    __syncthreads();
+
+    struct Row { uint32_t c[VW], wv[VW], ev[VW]; };
+    auto row = [&](int l) {
+        const uint32_t* t = lds + l * PITCH;
+        Row r;
+        load_words<VW, false>(t + kBandBody + lane * VW, r.c);
+        const uint32_t left = from_lower_lane(r.c[VW - 1], t[kBandLeft]);
+        const uint32_t right = from_upper_lane(r.c[0], t[RIGHT]);
+#pragma unroll
+        for (int k = 0; k < VW; ++k) {
+            r.wv[k] = west_of(r.c[k], k > 0 ? r.c[k - 1] : left);
+            r.ev[k] = east_of(r.c[k], k + 1 < VW ? r.c[k + 1] : right);
+        }
+        return r;
+    };
+    const int ob = nw * RW - 2;
+    const int o0 = w * ob / nw, o1 = (w + 1) * ob / nw;
+    Row up = row(o0), cur = row(o0 + 1);
+    for (int o = o0; o < o1; ++o) {
+        const Row dn = row(o + 2);
+        const int64_t y = y0 + o;
+        if (y < g.height && inside_row) {
+            uint32_t res[VW];
+#pragma unroll
+            for (int k = 0; k < VW; ++k) {
+                const uint32_t x = edge_word<MODE>(cur.c[k], up.ev[k], up.c[k], up.wv[k],
+                                                   cur.wv[k], dn.wv[k], dn.c[k], dn.ev[k],
+                                                   cur.ev[k]) & vm[k];
+                res[k] = invert ? (x ^ vm[k]) : x;
+            }
+            store_words<VW, true>(g.out + y * g.stride + jl, res);
+        }
+        up = cur;
+        cur = dn;
+    }
+}
+
 // ---------------------------------------------------------------- peeling ----
 
 // Iterated peeling of the edge (edge detection as the step that thinning

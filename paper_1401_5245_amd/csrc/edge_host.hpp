@@ -59,7 +59,10 @@ inline bool cfg_ok(const edge_launch_cfg& c) {
            c.cache_policy <= EDGE_CACHE_STREAM &&
            (c.shape == EDGE_SHAPE_STRIP ||
             ((c.shape == EDGE_SHAPE_TILE || c.shape == EDGE_SHAPE_TILE_XCD) &&
-             c.rows_per_tile <= EDGE_TILE_MAX_ROWS));
+             c.rows_per_tile <= EDGE_TILE_MAX_ROWS) ||
+            ((c.shape == EDGE_SHAPE_BAND || c.shape == EDGE_SHAPE_BAND_XCD) &&
+             (c.rows_per_tile == 1 || c.rows_per_tile == 2 || c.rows_per_tile == 4) &&
+             c.waves_per_block * c.rows_per_tile >= 3));
 }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -43,6 +43,20 @@ __global__ void __launch_bounds__(512) k_strip(Geom g, int64_t chunks, int rows,
     strip_unit<VW, MODE, Pol>(g, (int)(chunk * kWave * VW), (int)y0, (int)y1, bw, invert != 0);
 }
 
+// One image in bands (band_unit): one band of one chunk per workgroup of nw
+// wavefronts, nw * RW - 2 rows per band; by_xcd as for k_strip.
+template <int VW, int RW, int MODE>
+__global__ void __launch_bounds__(512) k_band(Geom g, int64_t chunks, int64_t nunits, uint32_t bw,
+                                              int invert, int nw, int by_xcd) {
+    extern __shared__ __align__(16) uint32_t band_lds[];
+    const uint32_t b = by_xcd ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    if ((int64_t)b >= nunits) return;      // the whole workgroup: no barrier is split
+    const int64_t band = (int64_t)b / chunks;
+    const int64_t chunk = (int64_t)b - band * chunks;
+    band_unit<VW, RW, MODE>(g, band_lds, nw, (int)(chunk * kWave * VW), band * (nw * RW - 2), bw,
+                            invert != 0);
+}
+
 // One image with rows of <= 32 words, `band` rows per wavefront.
 template <int MODE>
 __global__ void __launch_bounds__(512) k_narrow(Geom g, int64_t band, int64_t nunits, uint32_t bw,
@@ -522,9 +536,13 @@ using namespace edgeh;
 // Images of under 3 MiB of traffic are bound by launch latency and take
 // 2-row strips (the most wavefronts); larger ones take tiles in dispatch
 // order, 4 wavefronts per workgroup, of 4 rows up to 12 MiB, 8 rows up to
-// 64 MiB and 16 rows from there (uint64 squares, full definition, against
-// the strips this replaces: 4096^2 2.99 / 3.15 us, 8192^2 4.58 / 5.43,
-// 16384^2 13.48 / 14.23, 32768^2 49.1 / 50.0, 65536^2 189.4 / 192.6).
+// 64 MiB and 16 rows up to 96 MiB (uint64 squares, full definition, against
+// the strips these replace: 4096^2 2.99 / 3.15 us, 8192^2 4.58 / 5.43,
+// 16384^2 13.48 / 14.23); from 96 MiB, bands of 8 wavefronts x 2 rows
+// regrouped by XCD (against 16-row tiles: 23168^2 27.3 / 30.9 us, 32768^2
+// 49.5 / 49.9, 65536^2 166.7 / 188.5; 65536 x 16384 51.1 / 48.3). With 4
+// wavefronts per band the 65536^2 time varied from 172 to 208 us between
+// allocations and runs; with 8 it stays within 1%.
 edge_launch_cfg default_single(int64_t height, int64_t wd32) {
     edge_launch_cfg c{};
     c.blocks_per_cu = 1;
@@ -541,9 +559,13 @@ edge_launch_cfg default_single(int64_t height, int64_t wd32) {
         c.waves_per_block = 4;
         if (traffic < (3ll << 20)) {
             c.rows_per_tile = 2;
-        } else {
+        } else if (traffic < (96ll << 20)) {
             c.shape = EDGE_SHAPE_TILE;
             c.rows_per_tile = traffic < (12ll << 20) ? 4 : traffic < (64ll << 20) ? 8 : 16;
+        } else {
+            c.shape = EDGE_SHAPE_BAND_XCD;
+            c.rows_per_tile = 2;
+            c.waves_per_block = 8;
         }
     }
     return c;
@@ -603,6 +625,33 @@ int launch_strip(const Geom& g, int vw, int64_t chunks, const edge_launch_cfg& c
     return launch_status();
 }
 
+template <int MODE, int RW>
+int launch_band(const Geom& g, int vw, const edge_launch_cfg& c, uint32_t bw, int invert,
+                hipStream_t stream) {
+    const int nw = c.waves_per_block;
+    const int64_t chunks = ceil_div(g.wd, (int64_t)kWave * vw);
+    const int64_t nunits = chunks * ceil_div(g.height, (int64_t)(nw * RW - 2));
+    if (!grid_fits(nunits, nw * kWave)) return EDGE_ERR_UNSUPPORTED;
+    const size_t lds = (size_t)nw * RW * band_pitch(vw) * sizeof(uint32_t);
+    const int by_xcd = c.shape == EDGE_SHAPE_BAND_XCD;
+    const dim3 grid((uint32_t)nunits), block(nw * kWave);
+    switch (vw) {
+        case 4:
+            hipLaunchKernelGGL((k_band<4, RW, MODE>), grid, block, lds, stream, g, chunks, nunits,
+                               bw, invert, nw, by_xcd);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_band<2, RW, MODE>), grid, block, lds, stream, g, chunks, nunits,
+                               bw, invert, nw, by_xcd);
+            break;
+        default:
+            hipLaunchKernelGGL((k_band<1, RW, MODE>), grid, block, lds, stream, g, chunks, nunits,
+                               bw, invert, nw, by_xcd);
+            break;
+    }
+    return launch_status();
+}
+
 template <int MODE>
 int launch_single(const Geom& g, int vw, const edge_launch_cfg& c, uint32_t bw, int invert,
                   hipStream_t stream) {
@@ -620,8 +669,17 @@ int launch_single(const Geom& g, int vw, const edge_launch_cfg& c, uint32_t bw, 
     const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
     const int64_t blocks = ceil_div(nunits, c.waves_per_block);
     if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
-    // tiles for the edge map and its diagnostic and direction planes; the
-    // single-level peels (copy, one peel) always walk strips
+    // bands for the edge map and its diagnostic; tiles for those and the
+    // direction planes; the single-level peels (copy, one peel) always walk
+    // strips
+    const bool band = c.shape == EDGE_SHAPE_BAND || c.shape == EDGE_SHAPE_BAND_XCD;
+    if constexpr (MODE == kModePlain || MODE == kModeFull || MODE == kModeClause2) {
+        if (band && c.rows_per_tile == 1) return launch_band<MODE, 1>(g, vw, c, bw, invert, stream);
+        if (band && c.rows_per_tile == 2) return launch_band<MODE, 2>(g, vw, c, bw, invert, stream);
+        if (band) return launch_band<MODE, 4>(g, vw, c, bw, invert, stream);
+    } else {
+        if (band) return EDGE_ERR_UNSUPPORTED;
+    }
     if constexpr (MODE != kModeCopy && MODE != kModePeel) {
         const bool tile = c.shape == EDGE_SHAPE_TILE || c.shape == EDGE_SHAPE_TILE_XCD;
         if (tile && c.rows_per_tile <= 8)

@@ -1,6 +1,6 @@
 """Autotuner for launch configurations (words per lane, rows per tile,
-wavefronts per workgroup, persistent workgroups per CU, cache policy, strip
-or tile shape).
+wavefronts per workgroup, persistent workgroups per CU, cache policy, strip,
+tile or band shape).
 
 Each candidate is timed on the device from a captured graph of repeated
 launches (so host launch overhead does not decide), and is admitted only
@@ -138,6 +138,13 @@ def image_candidates(height: int, width: int, word_bits: int):
             continue
         yield dict(vec_words=vec, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=1,
                    cache_policy=0, shape=shape)
+    # bands (a workgroup's rows staged in LDS)
+    for vec, rows, waves, shape in itertools.product(
+            (2, 4), (1, 2, 4), (4, 8), (_abi.EDGE_SHAPE_BAND, _abi.EDGE_SHAPE_BAND_XCD)):
+        if waves * rows > max(4, height + 2):
+            continue
+        yield dict(vec_words=vec, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=1,
+                   cache_policy=0, shape=shape)
 
 
 def _rotate_time_us(fns, reps: int) -> float:
@@ -147,11 +154,13 @@ def _rotate_time_us(fns, reps: int) -> float:
 
 def tune_image(inp, out, height, width, *, mode="masks", border="white", candidates=None,
                cache: TuneCache | None = None, launches=20, reps=3, cold_bytes=512 << 20,
-               reference=None, verbose=False):
-    """Time every candidate on (inp, out); keep the fastest whose output
-    equals `reference` (a tensor like `out` holding the expected words, the
-    words out of the image's rows zero), or when it is None the output of
-    the built-in configuration. Returns (cfg, microseconds).
+               reference=None, verbose=False, finalists_n=3, finalist_rounds=4):
+    """Time every candidate on (inp, out) whose output equals `reference` (a
+    tensor like `out` holding the expected words, the words out of the
+    image's rows zero), or when it is None the output of the built-in
+    configuration; time the `finalists_n` fastest `finalist_rounds` more
+    times each and keep the one with the lowest median. Returns (cfg,
+    microseconds).
 
     Timing rotates over copies of the buffers until `cold_bytes` are
     touched per round, so images smaller than the last-level cache are
@@ -170,9 +179,15 @@ def tune_image(inp, out, height, width, *, mode="masks", border="white", candida
     copies = max(1, min(launches, -(-cold_bytes // per_pair)))
     ins = [inp] + [inp.clone() for _ in range(copies - 1)]
     outs = [out] + [torch.empty_like(out) for _ in range(copies - 1)]
-    best, best_us, tried = None, float("inf"), 0
+    timed, tried = [], 0
     cands = list(candidates) if candidates is not None else list(
         image_candidates(height, width, em.word_bits_of(inp)))
+
+    def time_us(c):
+        fns = [(lambda i=i: em.edge_image(ins[i], outs[i], height, width, mode=mode,
+                                          border=border, cfg=c)) for i in range(copies)]
+        return _rotate_time_us(fns * max(1, launches // copies), reps)
+
     for c in cands:
         out.zero_()
         em.edge_image(inp, out, height, width, mode=mode, border=border, cfg=c)
@@ -181,16 +196,28 @@ def tune_image(inp, out, height, width, *, mode="masks", border="white", candida
             if verbose:
                 print("rejected (output differs):", c)
             continue
-        fns = [(lambda i=i: em.edge_image(ins[i], outs[i], height, width, mode=mode,
-                                          border=border, cfg=c)) for i in range(copies)]
-        us = _rotate_time_us(fns * max(1, launches // copies), reps)
+        us = time_us(c)
         tried += 1
         if verbose:
             print(f"{us:9.2f} us  {c}")
-        if us < best_us:
-            best, best_us = c, us
-    if best is None:
+        timed.append((us, c))
+    if not timed:
         raise RuntimeError("no candidate configuration matched the reference output")
+    # one timing can flatter a shape whose speed varies from launch to
+    # launch: the fastest few are timed again, in turn, and the best median
+    # of all their timings wins
+    ranked = sorted(timed, key=lambda t: t[0])[:finalists_n]
+    finalists = [c for _, c in ranked]
+    runs = {i: [us] for i, (us, _) in enumerate(ranked)}
+    for _ in range(finalist_rounds):
+        for i, c in enumerate(finalists):
+            runs[i].append(time_us(c))
+    medians = {i: sorted(v)[len(v) // 2] for i, v in runs.items()}
+    pick = min(medians, key=medians.get)
+    best, best_us = finalists[pick], medians[pick]
+    if verbose:
+        for i, c in enumerate(finalists):
+            print(f"finalist {medians[i]:9.2f} us (of {[round(x, 2) for x in runs[i]]})  {c}")
     if cache is not None:
         cache.put(image_key(height, width, em.word_bits_of(inp), mode), best, best_us, tried)
     return best, best_us

@@ -66,7 +66,8 @@ int main(void) {
                                        {4, 2000, 4, 1, 0, 0}, {4, 4, 4, 33, 0, 0},
                                        {4, 4, 4, 1, 3, 0},   {4, 4, 4, 1, -1, 0},
                                        {4, EDGE_TILE_MAX_ROWS + 1, 4, 1, 0, EDGE_SHAPE_TILE},
-                                       {4, 4, 4, 1, 0, 3},   {4, 4, 4, 1, 0, -1}};
+                                       {4, 4, 4, 1, 0, 5},   {4, 4, 4, 1, 0, -1},
+                                       {4, 3, 4, 1, 0, EDGE_SHAPE_BAND}, {4, 2, 1, 1, 0, EDGE_SHAPE_BAND}};
         for (unsigned i = 0; i < sizeof bad / sizeof bad[0]; ++i) {
             edge_launch_cfg* c = (edge_launch_cfg*)malloc(sizeof *c);
             *c = bad[i];

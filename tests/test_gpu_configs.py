@@ -6,7 +6,8 @@ loop) that those workloads run.
 Workloads: a 512x512 stroke image (seed 1, uint32 rows); an 8192x8192 glyph
 page (seed 2, uint64 rows) with the built-in and the autotuned shape; a
 16384x16384 skeleton page (seed 4, uint64 rows) in full mode and its
-clause-2 diagnostic; 4096 glyph crops (seed 3, uint32 rows) in one
+clause-2 diagnostic; a 12800x32768 glyph page (seed 12) in the built-in
+band shape; 4096 glyph crops (seed 3, uint32 rows) in one
 persistent launch with the autotuned shape, replayed from a captured graph.
 Every output word is compared with the oracle's edge map of section 1."""
 import numpy as np
@@ -64,6 +65,20 @@ def test_skeleton_page_16384_u64_full_and_clause2():
         log(f"16384^2 u64 skeleton page clause 2 cfg={cfg}")
         assert_same(_whole(img, 64, mode="full", clause2_only=True, cfg=cfg), want_c2,
                     f"16384^2 clause 2 cfg={cfg}")
+
+
+def test_glyph_page_12800x32768_u64_builtin_band():
+    """From 96 MiB of traffic the built-in shape is a band (a workgroup's
+    rows staged in LDS): a whole 12800 x 32768 page in full mode."""
+    import ctypes
+    from paper_1401_5245_amd import _abi
+    c = _abi.EdgeLaunchCfg()
+    assert _abi.load().edge_default_cfg(12800, 32768, 64, 1, 0, ctypes.byref(c)) == 0
+    assert c.shape == _abi.EDGE_SHAPE_BAND_XCD
+    img = images.glyph_page(12800, 32768, seed=12)
+    log("12800x32768 u64 glyph page full, built-in band")
+    assert_same(_whole(img, 64, mode="full"),
+                oracle.edge(img, clauses=oracle.CLAUSE1 | oracle.CLAUSE2), "12800x32768 band")
 
 
 def test_4096_glyph_crops_tuned_graph_replays():

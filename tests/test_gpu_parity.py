@@ -116,6 +116,25 @@ def test_tile_configs(vec, rows, waves, shape):
             assert_same(got, want, f"{cfg} {H}x{W} B{wb} {mode} c2={c2} {border} inv={inv}")
 
 
+@pytest.mark.parametrize("vec", [1, 2, 4])
+@pytest.mark.parametrize("rows", [1, 2, 4])
+@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+@pytest.mark.parametrize("shape", [3, 4])
+def test_band_configs(vec, rows, waves, shape):
+    """Bands (a workgroup's rows staged in LDS, all loaded at once) of every
+    height, in both workgroup orders, against the oracle."""
+    if waves * rows < 3:
+        pytest.skip("a band computes waves * rows - 2 >= 1 rows")
+    cfg = dict(vec_words=vec, rows_per_tile=rows, waves_per_block=waves, blocks_per_cu=1,
+               cache_policy=0, shape=shape)
+    for (H, W, wb) in TILE_IMAGES:
+        for (mode, c2, border, inv) in TILE_CASES:
+            img, want = _tile_case(H, W, mode, c2, border, inv)
+            _, got = run_single(img, wb, mode=mode, clause2_only=c2, border=border, invert=inv,
+                                cfg=cfg)
+            assert_same(got, want, f"{cfg} {H}x{W} B{wb} {mode} c2={c2} {border} inv={inv}")
+
+
 @pytest.mark.parametrize("H,W,wb", [(1600, 8200, 64), (1200, 12000, 32), (3300, 4100, 64)])
 def test_builtin_tiles(H, W, wb):
     """Images of 3 MiB of traffic and more take tiles by default: whole
