@@ -465,7 +465,7 @@ def plain_65536(torch, em, tm, steps):
     torch.cuda.empty_cache()
     return {"workload": "plain, 65536x65536 tiled glyph page (seed 22), uint64, 1 GiB per launch",
             "gpx_s": round(H * W / (ms * 1e-3) / 1e9, 1), "ms_per_launch": round(ms, 4),
-            "roofline": roofline(nbytes, ms, measured_traffic("k_strip_plain_65536x65536_u64.md")),
+            "roofline": roofline(nbytes, ms, measured_traffic("k_band_plain_65536x65536_u64.md")),
             "sampled_rows_bit_exact": ok}
 
 
@@ -517,7 +517,7 @@ def full_65536(torch, em, tm, steps=10):
         key = "full" if mode == "full" else "plain"
         res[key] = {"ms_per_launch": round(ms, 4), "gpx_s": round(H * W / (ms * 1e-3) / 1e9, 1),
                     "roofline": roofline(nbytes, ms, measured_traffic(
-                        "k_strip_full_65536x65536_u64.md") if mode == "full" else None),
+                        "k_band_full_65536x65536_u64.md") if mode == "full" else None),
                     "sampled_rows_bit_exact": ok and (ok2 if mode == "full" else True)}
     res["full_vs_plain_time"] = round(res["full"]["ms_per_launch"] / res["plain"]["ms_per_launch"],
                                       4)
