@@ -535,10 +535,12 @@ using namespace edgeh;
 // wavefronts: 3.1 against 4.4 us at 4096^2, 5.2 against 7.1 us at 6000^2).
 // Images of under 3 MiB of traffic are bound by launch latency and take
 // 2-row strips (the most wavefronts); larger ones take tiles in dispatch
-// order, 4 wavefronts per workgroup, of 4 rows up to 12 MiB, 8 rows up to
-// 64 MiB and 16 rows up to 96 MiB (uint64 squares, full definition, against
-// the strips these replace: 4096^2 2.99 / 3.15 us, 8192^2 4.58 / 5.43,
-// 16384^2 13.48 / 14.23); from 96 MiB, bands of 8 wavefronts x 2 rows
+// order, 4 wavefronts per workgroup, of 4 rows up to 12 MiB and 8 rows up
+// to 64 MiB, then 16-row tiles of 8 wavefronts regrouped by XCD up to 96 MiB
+// (uint64 squares, full definition, against the strips these replace:
+// 4096^2 2.99 / 3.15 us, 8192^2 4.58 / 5.43, 16384^2 13.3 / 14.2; at
+// 16384^2 the 16-row tiles take 13.5 us in dispatch order with 4
+// wavefronts); from 96 MiB, bands of 8 wavefronts x 2 rows
 // regrouped by XCD (against 16-row tiles: 23168^2 27.3 / 30.9 us, 32768^2
 // 49.5 / 49.9, 65536^2 166.7 / 188.5; 65536 x 16384 51.1 / 48.3). With 4
 // wavefronts per band the 65536^2 time varied from 172 to 208 us between
@@ -559,9 +561,13 @@ edge_launch_cfg default_single(int64_t height, int64_t wd32) {
         c.waves_per_block = 4;
         if (traffic < (3ll << 20)) {
             c.rows_per_tile = 2;
-        } else if (traffic < (96ll << 20)) {
+        } else if (traffic < (64ll << 20)) {
             c.shape = EDGE_SHAPE_TILE;
-            c.rows_per_tile = traffic < (12ll << 20) ? 4 : traffic < (64ll << 20) ? 8 : 16;
+            c.rows_per_tile = traffic < (12ll << 20) ? 4 : 8;
+        } else if (traffic < (96ll << 20)) {
+            c.shape = EDGE_SHAPE_TILE_XCD;
+            c.rows_per_tile = 16;
+            c.waves_per_block = 8;
         } else {
             c.shape = EDGE_SHAPE_BAND_XCD;
             c.rows_per_tile = 2;
@@ -669,16 +675,15 @@ int launch_single(const Geom& g, int vw, const edge_launch_cfg& c, uint32_t bw, 
     const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
     const int64_t blocks = ceil_div(nunits, c.waves_per_block);
     if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
-    // bands for the edge map and its diagnostic; tiles for those and the
+    // bands for the edge map and its diagnostic (the direction planes walk
+    // a band shape as strips of rows_per_tile rows); tiles for those and the
     // direction planes; the single-level peels (copy, one peel) always walk
     // strips
-    const bool band = c.shape == EDGE_SHAPE_BAND || c.shape == EDGE_SHAPE_BAND_XCD;
     if constexpr (MODE == kModePlain || MODE == kModeFull || MODE == kModeClause2) {
+        const bool band = c.shape == EDGE_SHAPE_BAND || c.shape == EDGE_SHAPE_BAND_XCD;
         if (band && c.rows_per_tile == 1) return launch_band<MODE, 1>(g, vw, c, bw, invert, stream);
         if (band && c.rows_per_tile == 2) return launch_band<MODE, 2>(g, vw, c, bw, invert, stream);
         if (band) return launch_band<MODE, 4>(g, vw, c, bw, invert, stream);
-    } else {
-        if (band) return EDGE_ERR_UNSUPPORTED;
     }
     if constexpr (MODE != kModeCopy && MODE != kModePeel) {
         const bool tile = c.shape == EDGE_SHAPE_TILE || c.shape == EDGE_SHAPE_TILE_XCD;

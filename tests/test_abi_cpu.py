@@ -82,11 +82,6 @@ def test_mode_flag_and_cfg_validation():
                 (4, 2, 1, 1, 0, _abi.EDGE_SHAPE_BAND)):
         cfg = _abi.EdgeLaunchCfg(*bad)
         assert launch(cfg=ctypes.byref(cfg)) == INVALID, bad
-    # direction planes take no bands (rows wider than 32 words; the call
-    # returns before any HIP call)
-    band = _abi.EdgeLaunchCfg(4, 2, 4, 1, 0, _abi.EDGE_SHAPE_BAND)
-    assert lib.edge_directions(A, B, 4 * 100, 4, 4000, 100, 64, 0, ctypes.byref(band),
-                               None) == _abi.EDGE_ERR_UNSUPPORTED
     # tiles up to EDGE_TILE_MAX_ROWS rows pass the checks (the launch
     # itself is not reached: H = 0)
     ok = _abi.EdgeLaunchCfg(4, _abi.EDGE_TILE_MAX_ROWS, 4, 1, 0, _abi.EDGE_SHAPE_TILE)
@@ -123,11 +118,11 @@ def test_default_cfg():
     assert lib.edge_default_cfg(100, 100, 32, 0, 1, ctypes.byref(c)) == OK
     assert c.blocks_per_cu >= 1
     # built-in shape of uint64 squares: 2-row strips under 3 MiB of traffic,
-    # then tiles of 4 rows (to 12 MiB), 8 rows (to 64 MiB) and 16 rows (to
-    # 96 MiB), then 2-row bands
+    # then tiles of 4 rows (to 12 MiB), 8 rows (to 64 MiB) and 16 rows
+    # regrouped by XCD (to 96 MiB), then 2-row bands
     for side, shape, rows in ((2048, _abi.EDGE_SHAPE_STRIP, 2), (4096, _abi.EDGE_SHAPE_TILE, 4),
                               (8192, _abi.EDGE_SHAPE_TILE, 8), (11584, _abi.EDGE_SHAPE_TILE, 8),
-                              (16384, _abi.EDGE_SHAPE_TILE, 16),
+                              (16384, _abi.EDGE_SHAPE_TILE_XCD, 16),
                               (23168, _abi.EDGE_SHAPE_BAND_XCD, 2),
                               (65536, _abi.EDGE_SHAPE_BAND_XCD, 2)):
         assert lib.edge_default_cfg(side, side, 64, 0, 0, ctypes.byref(c)) == OK
