@@ -360,6 +360,9 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
     constexpr int P = Pol::prefetch;
     const int lane = threadIdx.x & (kWave - 1);
     const int jl = j0 + lane * VW;
+    // the display inversion as a mask: (x ^ inv) & vm is the edge word,
+    // inverted or not, with its pad bits cleared (one three-input operation)
+    const uint32_t inv = invert ? 0xffffffffu : 0u;
 
     uint32_t vm[VW], om[VW];
 #pragma unroll
@@ -437,9 +440,8 @@ __device__ __forceinline__ void strip_body(const Geom& g, int j0, int y0, int y1
             uint32_t res[VW];
 #pragma unroll
             for (int k = 0; k < VW; ++k) {
-                const uint32_t v = edge_word<MODE>(cur.c[k], up.e[k], up.c[k], up.w[k], cur.w[k],
-                                                   dn.w[k], dn.c[k], dn.e[k], cur.e[k]) & vm[k];
-                res[k] = invert ? (v ^ vm[k]) : v;
+                res[k] = (edge_word<MODE>(cur.c[k], up.e[k], up.c[k], up.w[k], cur.w[k], dn.w[k],
+                                          dn.c[k], dn.e[k], cur.e[k]) ^ inv) & vm[k];
             }
             store_row(op, res);
         }
@@ -630,6 +632,7 @@ __device__ __forceinline__ void band_unit(const Geom& g, uint32_t* lds, int nw, 
         vm[k] = valid_bits(jl + k, g.width);
         om[k] = bw & ~vm[k];
     }
+    const uint32_t inv = invert ? 0xffffffffu : 0u;    // as in strip_body
     const bool has_l = j0 > 0, has_r = j0 + kWave * VW < g.wd;
     // lane 0 loads the word left of the chunk, lane 63 the word right of it
     // (when inside the row); the other lanes load the chunk's first word
@@ -684,12 +687,9 @@ __device__ __forceinline__ void band_unit(const Geom& g, uint32_t* lds, int nw, 
         if (y < g.height && inside_row) {
             uint32_t res[VW];
 #pragma unroll
-            for (int k = 0; k < VW; ++k) {
-                const uint32_t x = edge_word<MODE>(cur.c[k], up.ev[k], up.c[k], up.wv[k],
-                                                   cur.wv[k], dn.wv[k], dn.c[k], dn.ev[k],
-                                                   cur.ev[k]) & vm[k];
-                res[k] = invert ? (x ^ vm[k]) : x;
-            }
+            for (int k = 0; k < VW; ++k)
+                res[k] = (edge_word<MODE>(cur.c[k], up.ev[k], up.c[k], up.wv[k], cur.wv[k],
+                                          dn.wv[k], dn.c[k], dn.ev[k], cur.ev[k]) ^ inv) & vm[k];
             store_words<VW, true>(g.out + y * g.stride + jl, res);
         }
         up = cur;

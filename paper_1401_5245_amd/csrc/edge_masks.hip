@@ -572,6 +572,14 @@ edge_launch_cfg default_single(int64_t height, int64_t wd32) {
             c.shape = EDGE_SHAPE_BAND_XCD;
             c.rows_per_tile = 2;
             c.waves_per_block = 8;
+            // a band grid past the dispatch limit (images of tens of GB):
+            // long strips, whose grid is 128 times smaller
+            const int64_t span = (int64_t)kWave * strip_vw(wd32, c.vec_words, 0, 0);
+            const int64_t bands = ceil_div(wd32, span) * ceil_div(height, (int64_t)(8 * 2 - 2));
+            if (!grid_fits(bands, 8 * kWave)) {
+                c.shape = EDGE_SHAPE_STRIP;
+                c.rows_per_tile = 256;
+            }
         }
     }
     return c;

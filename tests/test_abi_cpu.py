@@ -129,6 +129,11 @@ def test_default_cfg():
         assert (c.shape, c.rows_per_tile) == (shape, rows), (side, c.shape, c.rows_per_tile)
         assert c.rows_per_tile <= _abi.EDGE_TILE_MAX_ROWS or c.shape == _abi.EDGE_SHAPE_STRIP
         assert c.shape != _abi.EDGE_SHAPE_BAND_XCD or c.waves_per_block * c.rows_per_tile >= 3
+    # past the dispatch limit of a band grid (2^32 work-items), long strips
+    assert lib.edge_default_cfg(1 << 25, 65536, 64, 0, 0, ctypes.byref(c)) == OK
+    assert (c.shape, c.rows_per_tile) == (_abi.EDGE_SHAPE_STRIP, 256)
+    assert lib.edge_default_cfg(1 << 20, 65536, 64, 0, 0, ctypes.byref(c)) == OK
+    assert c.shape == _abi.EDGE_SHAPE_BAND_XCD
     # rows of at most 32 words: narrow units whatever the size
     assert lib.edge_default_cfg(65536, 1024, 32, 0, 0, ctypes.byref(c)) == OK
     assert c.vec_words == 1 and c.shape == _abi.EDGE_SHAPE_STRIP
