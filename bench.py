@@ -212,20 +212,22 @@ class StepTimer:
     from one captured graph, or (eager=True) issued from the host one call
     at a time, for kernels that take longer than a host call.
 
-    Warm-up runs the launches until at least `warmup` launches and `warm_ms`
-    of them have run. Before each timed region a spin kernel keeps the GPU
-    busy while the host submits the graph or the calls (eager: long enough
-    for all of them, from the host time per call measured in the warm-up),
-    so the two events bracket device time only: event -> launches -> event.
-    A graph replay adds about 10 us per region (20 launches of the headline:
-    13.4 us per launch replayed, 13.1 us issued; equal over 200)."""
+    Warm-up replays the graph (launches back to back whatever the host's
+    speed, also under a tracing profiler) until at least `warmup` launches
+    and `warm_ms` of them have run. Before each timed region a spin kernel
+    keeps the GPU busy while the host submits the graph or the calls
+    (eager: long enough for all of them, from the host time of one pass of
+    the calls after the warm-up), so the two events bracket device time
+    only: event -> launches -> event. A graph replay adds about 10 us per
+    region (20 launches of the headline: 13.4 us per launch replayed, 13.1
+    us issued; equal over 200)."""
 
     def __init__(self, torch, fns, steps: int, eager: bool = False):
         self.torch = torch
         self.steps = steps
         self.eager = eager
         self.seq = [fns[i % len(fns)] for i in range(steps)]
-        self.graph = None if eager else graph_of(torch, None, nstreams=1, fns=self.seq)
+        self.graph = graph_of(torch, None, nstreams=1, fns=self.seq)
         self.sleep_cycles = self._calibrate_sleep()
 
     def _run(self):
@@ -251,17 +253,24 @@ class StepTimer:
     def warm(self, warmup: int, warm_ms: float = 20.0) -> int:
         t = self.torch
         done, t0 = 0, time.perf_counter()
-        host_s = 0.0
         while done < max(warmup, 1) or (time.perf_counter() - t0) * 1e3 < warm_ms:
-            h0 = time.perf_counter()
-            self._run()
-            host_s = max(host_s, time.perf_counter() - h0)
+            self.graph.replay()
             done += self.steps
             t.cuda.synchronize()
-        if self.eager and self.sleep_cycles:
-            # the spin must outlast the host's submission of every call
-            need_ms = 1.5 * host_s * 1e3 + 0.5
-            self.sleep_cycles = int(min(self.sleep_cycles * max(1.0, need_ms / 0.5), 1 << 31))
+        if self.eager:
+            # one pass of the calls, its host time sizing the spin: the spin
+            # must outlast the host's submission of every call of a region
+            if self.sleep_cycles:
+                t.cuda._sleep(self.sleep_cycles)
+            h0 = time.perf_counter()
+            self._run()
+            host_ms = (time.perf_counter() - h0) * 1e3
+            t.cuda.synchronize()
+            done += self.steps
+            if self.sleep_cycles:
+                need_ms = 1.5 * host_ms + 0.5
+                self.sleep_cycles = int(min(self.sleep_cycles * max(1.0, need_ms / 0.5),
+                                            1 << 31))
         return done
 
     def region_ms(self) -> float:
