@@ -65,6 +65,27 @@ def test_strides_pads_and_alignment(word_bits):
                 assert_same(got, want, f"stride+{stride_extra} off{offset_w} pad={pad}")
 
 
+@pytest.mark.parametrize("cfg", [dict(vec_words=4, rows_per_tile=16, waves_per_block=8, shape=2),
+                                 dict(vec_words=4, rows_per_tile=7, waves_per_block=2, shape=1),
+                                 dict(vec_words=4, rows_per_tile=2, waves_per_block=8, shape=4),
+                                 dict(vec_words=2, rows_per_tile=4, waves_per_block=1, shape=3)])
+@pytest.mark.parametrize("word_bits", [32, 64])
+def test_strides_pads_and_alignment_tiles_bands(cfg, word_bits):
+    """Tiles and bands over garbage pad bits, stride padding (never written)
+    and pointers off the 16-byte boundary (fewer words per lane)."""
+    img = rand_img(50, 3000, 0.5, seed=19)
+    for mode, c2 in (("masks", False), ("full", True)):
+        want = expect(img, mode=mode, clause2_only=c2)
+        for stride_extra in (0, 1, 3):
+            for offset_w in (0, 1, 2, 3):
+                for pad in ("ones", "random"):
+                    _, got = run_single(img, word_bits, stride_extra=stride_extra, pad=pad,
+                                        offset_words=offset_w, mode=mode, clause2_only=c2,
+                                        cfg=cfg)
+                    assert_same(got, want, f"{cfg} B{word_bits} stride+{stride_extra} "
+                                           f"off{offset_w} pad={pad} {mode}")
+
+
 @pytest.mark.parametrize("vec", [1, 2, 4])
 @pytest.mark.parametrize("rows", [1, 3, 4, 5, 8, 17, 64])
 @pytest.mark.parametrize("waves", [1, 2, 4, 8])
