@@ -764,6 +764,18 @@ int image_launch(const void* in, void* out, int64_t height, int64_t width, int64
     vmax = std::min(vmax, alignment_words(pout));
     if (planes > 1) vmax = std::min(vmax, alignment_words((uintptr_t)(plane_words * word_bytes)));
     const int vw = strip_vw(g.wd, vmax, 0, g.stride);
+    // four planes from rows of four words per lane and 12 MiB - 1 GiB of
+    // image traffic: 8-row tiles (against the 2-row strips: 8192^2 8.1 /
+    // 10.2 us, 16384^2 34.7 / 38.2, 23168^2 83.9 / 88.8, 32768^2 125 / 151;
+    // at 4096^2, with two words per lane (11584^2) and at 65536^2 the
+    // strips are as fast or faster)
+    const int64_t image_traffic = (int64_t)2 * span_words * word_bytes;
+    if (!cfg && planes == 4 && g.wd > kNarrowMaxWords && vw == 4 &&
+        image_traffic >= (12ll << 20) && image_traffic < (1ll << 30)) {
+        c.shape = EDGE_SHAPE_TILE;
+        c.rows_per_tile = 8;
+        c.waves_per_block = 4;
+    }
     const uint32_t bw = border_word(border);
     const int inv = (flags & EDGE_FLAG_INVERT_OUT) ? 1 : 0;
     hipStream_t s = (hipStream_t)hip_stream;

@@ -43,6 +43,22 @@ def test_direction_planes(word_bits, H, W):
             assert_same(ors, unpack_rows(mask.cpu().numpy().view(words.dtype), W), "OR of planes")
 
 
+def test_direction_planes_builtin_tiles():
+    """From 12 MiB of image traffic, rows of four words per lane take 8-row
+    tiles by default: a whole 3200 x 16384 page against the oracle."""
+    import paper_1401_5245_amd as em
+    img = images.glyph_page(3200, 16384, seed=9, noise=0.02)
+    words = pack_rows(img, 64, pad="random", seed=9)
+    inp = to_device_words(words)
+    out = torch.empty((4,) + tuple(inp.shape), dtype=inp.dtype, device="cuda")
+    em.edge_directions(inp, out, *img.shape)
+    torch.cuda.synchronize()
+    want = oracle.fundamental_edges(img)
+    host = out.cpu().numpy().view(np.uint64)
+    for k in range(4):
+        assert_same(unpack_rows(host[k], img.shape[1]), want[k], oracle.DIRECTIONS[k])
+
+
 @pytest.mark.parametrize("cfg", [dict(vec_words=1, rows_per_tile=3, waves_per_block=2),
                                  dict(vec_words=4, rows_per_tile=16, waves_per_block=8,
                                       cache_policy=2),
