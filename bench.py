@@ -411,8 +411,10 @@ def copy_ceiling(torch, em, tm, nbytes, nb, steps):
 
 def launch_floor_ms(torch, em, tm, nl=40, reps=10, trials=7, warm=50):
     """Per-launch time of a near-empty kernel (the library's copy of 16
-    bytes: one workgroup) replayed from a one-stream graph, as the headline
-    launches are: the fixed cost any launch pays. Warmed up first (it may
+    bytes: one workgroup) replayed from a one-stream graph, launches back
+    to back as the headline's are: the fixed cost any launch pays. (Issued
+    one call at a time, a launch this short would be bound by the host.)
+    Warmed up first (it may
     follow seconds of host-only work, after which the GPU idles at lower
     clocks) and the median of several trials."""
     a = torch.zeros(2, dtype=torch.int64, device="cuda")
