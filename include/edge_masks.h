@@ -137,10 +137,10 @@ typedef struct edge_image_desc {
  *                   EDGE_SHAPE_BAND_XCD (a workgroup loads
  *                   waves_per_block * rows_per_tile consecutive rows of one
  *                   chunk into LDS at once and computes all but the first
- *                   and last; non-temporal loads and stores; edge-map calls:
- *                   edge_directions walks a band shape as strips of
- *                   rows_per_tile rows). Ignored by batches, by rows of at
- *                   most 32 words and by the grey-input and peeling calls. */
+ *                   and last; non-temporal loads and stores). Used by the
+ *                   edge-map calls and edge_directions; ignored by batches,
+ *                   by rows of at most 32 words and by the grey-input and
+ *                   peeling calls. */
 typedef struct edge_launch_cfg {
     int32_t vec_words;
     int32_t rows_per_tile;

@@ -685,12 +685,31 @@ __device__ __forceinline__ void band_unit(const Geom& g, uint32_t* lds, int nw, 
         const Row dn = row(o + 2);
         const int64_t y = y0 + o;
         if (y < g.height && inside_row) {
-            uint32_t res[VW];
+            uint32_t* op = g.out + y * g.stride + jl;
+            if constexpr (MODE == kModeDirections) {
+                // the four fundamental edges (section 4), as in strip_body
+                uint32_t l[VW], r[VW], u[VW], d[VW];
 #pragma unroll
-            for (int k = 0; k < VW; ++k)
-                res[k] = (edge_word<MODE>(cur.c[k], up.ev[k], up.c[k], up.wv[k], cur.wv[k],
-                                          dn.wv[k], dn.c[k], dn.ev[k], cur.ev[k]) ^ inv) & vm[k];
-            store_words<VW, true>(g.out + y * g.stride + jl, res);
+                for (int k = 0; k < VW; ++k) {
+                    const uint32_t m = ~cur.c[k] & vm[k];
+                    l[k] = m & cur.wv[k];
+                    r[k] = m & cur.ev[k];
+                    u[k] = m & up.c[k];
+                    d[k] = m & dn.c[k];
+                }
+                store_words<VW, true>(op, l);
+                store_words<VW, true>(op + g.plane, r);
+                store_words<VW, true>(op + 2 * g.plane, u);
+                store_words<VW, true>(op + 3 * g.plane, d);
+            } else {
+                uint32_t res[VW];
+#pragma unroll
+                for (int k = 0; k < VW; ++k)
+                    res[k] = (edge_word<MODE>(cur.c[k], up.ev[k], up.c[k], up.wv[k], cur.wv[k],
+                                              dn.wv[k], dn.c[k], dn.ev[k], cur.ev[k]) ^ inv) &
+                             vm[k];
+                store_words<VW, true>(op, res);
+            }
         }
         up = cur;
         cur = dn;

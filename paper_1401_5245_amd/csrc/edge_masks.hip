@@ -683,11 +683,10 @@ int launch_single(const Geom& g, int vw, const edge_launch_cfg& c, uint32_t bw, 
     const int64_t nunits = chunks * ceil_div(g.height, c.rows_per_tile);
     const int64_t blocks = ceil_div(nunits, c.waves_per_block);
     if (!grid_fits(blocks, c.waves_per_block * kWave)) return EDGE_ERR_UNSUPPORTED;
-    // bands for the edge map and its diagnostic (the direction planes walk
-    // a band shape as strips of rows_per_tile rows); tiles for those and the
-    // direction planes; the single-level peels (copy, one peel) always walk
-    // strips
-    if constexpr (MODE == kModePlain || MODE == kModeFull || MODE == kModeClause2) {
+    // bands and tiles for the edge map, its diagnostic and the direction
+    // planes; the single-level peels (copy, one peel) always walk strips
+    if constexpr (MODE == kModePlain || MODE == kModeFull || MODE == kModeClause2 ||
+                  MODE == kModeDirections) {
         const bool band = c.shape == EDGE_SHAPE_BAND || c.shape == EDGE_SHAPE_BAND_XCD;
         if (band && c.rows_per_tile == 1) return launch_band<MODE, 1>(g, vw, c, bw, invert, stream);
         if (band && c.rows_per_tile == 2) return launch_band<MODE, 2>(g, vw, c, bw, invert, stream);
@@ -764,17 +763,30 @@ int image_launch(const void* in, void* out, int64_t height, int64_t width, int64
     vmax = std::min(vmax, alignment_words(pout));
     if (planes > 1) vmax = std::min(vmax, alignment_words((uintptr_t)(plane_words * word_bytes)));
     const int vw = strip_vw(g.wd, vmax, 0, g.stride);
-    // four planes from rows of four words per lane and 12 MiB - 1 GiB of
-    // image traffic: 8-row tiles (against the 2-row strips: 8192^2 8.1 /
-    // 10.2 us, 16384^2 34.7 / 38.2, 23168^2 83.9 / 88.8, 32768^2 125 / 151;
-    // at 4096^2, with two words per lane (11584^2) and at 65536^2 the
-    // strips are as fast or faster)
+    // four planes from rows of four words per lane: 8-row tiles for 12 MiB
+    // - 1 GiB of image traffic (against the 2-row strips: 8192^2 8.1 /
+    // 10.2 us, 16384^2 34.7 / 38.2, 23168^2 83.9 / 88.8, 32768^2 125 /
+    // 151), bands of 8 wavefronts x 2 rows from there (65536^2: 481 against
+    // 499-520 us); at 4096^2 and with two words per lane (11584^2) the
+    // strips are as fast or faster
     const int64_t image_traffic = (int64_t)2 * span_words * word_bytes;
     if (!cfg && planes == 4 && g.wd > kNarrowMaxWords && vw == 4 &&
-        image_traffic >= (12ll << 20) && image_traffic < (1ll << 30)) {
-        c.shape = EDGE_SHAPE_TILE;
-        c.rows_per_tile = 8;
-        c.waves_per_block = 4;
+        image_traffic >= (12ll << 20)) {
+        if (image_traffic < (1ll << 30)) {
+            c.shape = EDGE_SHAPE_TILE;
+            c.rows_per_tile = 8;
+            c.waves_per_block = 4;
+        } else {
+            c.shape = EDGE_SHAPE_BAND;
+            c.rows_per_tile = 2;
+            c.waves_per_block = 8;
+            const int64_t bands = ceil_div(g.wd, (int64_t)kWave * 4) * ceil_div(height, (int64_t)14);
+            if (!grid_fits(bands, 8 * kWave)) {         // as in default_single
+                c.shape = EDGE_SHAPE_STRIP;
+                c.rows_per_tile = 2;
+                c.waves_per_block = 4;
+            }
+        }
     }
     const uint32_t bw = border_word(border);
     const int inv = (flags & EDGE_FLAG_INVERT_OUT) ? 1 : 0;

@@ -64,7 +64,9 @@ def test_direction_planes_builtin_tiles():
                                       cache_policy=2),
                                  dict(vec_words=4, rows_per_tile=7, waves_per_block=4, shape=1),
                                  dict(vec_words=2, rows_per_tile=16, waves_per_block=2, shape=2),
-                                 dict(vec_words=4, rows_per_tile=2, waves_per_block=8, shape=4)])
+                                 dict(vec_words=4, rows_per_tile=2, waves_per_block=8, shape=4),
+                                 dict(vec_words=2, rows_per_tile=4, waves_per_block=2, shape=3),
+                                 dict(vec_words=1, rows_per_tile=1, waves_per_block=4, shape=3)])
 def test_direction_planes_cfgs(cfg):
     import paper_1401_5245_amd as em
     img = images.glyph_page(300, 3000, seed=8, noise=0.02)
