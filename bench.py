@@ -124,10 +124,11 @@ def words_tensor(torch, words):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_strip_full_16384x16384_u64.md")
-# the unit that holds the edge, batch and copy kernels, and what it includes
-KERNEL_SOURCES = ("paper_1401_5245_amd/csrc/edge_device.hpp",
-                  "paper_1401_5245_amd/csrc/edge_host.hpp",
-                  "paper_1401_5245_amd/csrc/edge_masks.hip")
+# every kernel source of the library (a change to any of them voids the
+# traffic figures of the profile summaries)
+KERNEL_SOURCES = tuple(sorted(
+    "paper_1401_5245_amd/csrc/" + f for f in os.listdir(os.path.join(ROOT, "paper_1401_5245_amd", "csrc"))
+    if f.endswith((".hip", ".hpp"))))
 
 
 def measured_traffic(path: str = PROFILE, index: int = 0):

@@ -197,7 +197,8 @@ int edge_directions(const void* in, void* out4, int64_t plane_words, int64_t hei
  * Any pointer and pitch: bytes load in the 16-byte aligned blocks that hold
  * them (two per 32 pixels where rows start on 16-byte boundaries, three
  * otherwise); a block can reach up to 15 bytes before a row's first byte
- * or after its last, never outside the memory pages of the row. */
+ * or after its last, never outside the memory pages of the row. Packed
+ * output of 16 MiB or more (height x row words) is stored non-temporally. */
 int edge_threshold_pack(const void* grey, int64_t grey_stride_bytes, int threshold, void* out,
                         int64_t height, int64_t width, int64_t stride_words, int word_bits,
                         void* hip_stream);
@@ -211,9 +212,10 @@ int edge_threshold_pack(const void* grey, int64_t grey_stride_bytes, int thresho
  * waves_per_block x r rows of a chunk at once (r = rows_per_tile rounded
  * down to 2, 4 or 8, raised until a band loads four rows) and writes the
  * rows between the first and the last. cfg: NULL for the built-in shape
- * (8 wavefronts, r = 2, cached), or a configuration; vec_words and
- * blocks_per_cu are ignored; cache_policy STREAM makes the loads and stores
- * non-temporal, AUTO and NORMAL keep them cached. */
+ * (8 wavefronts, r = 2, cache_policy AUTO), or a configuration; vec_words
+ * and blocks_per_cu are ignored; cache_policy AUTO keeps the loads cached
+ * and makes the stores non-temporal, NORMAL keeps both cached, STREAM makes
+ * both non-temporal. */
 int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int threshold, void* out,
                          int64_t height, int64_t width, int64_t stride_words, int word_bits,
                          int border, int mode, uint32_t flags, const edge_launch_cfg* cfg,

@@ -66,6 +66,9 @@ struct StripPolicy {
 // the output stay cached for the next consumer); large images stream.
 using CachedStrip = StripPolicy<4, false, false>;
 using StreamingStrip = StripPolicy<4, true, true>;
+// Rows that are re-read from the cache (the halo rows of grey bands) but
+// whose output is not: cached loads, non-temporal stores.
+using StreamOutStrip = StripPolicy<4, false, true>;
 // Tiles: a wavefront requests all rows of its tile and the two halo rows
 // at once, computes the rows as they arrive and ends. Short-lived
 // wavefronts with their whole input in flight keep the memory system's

@@ -34,7 +34,9 @@ __global__ void __launch_bounds__(512) k_grey_band(Geom g, int64_t chunks, int64
 // blocks that hold its 32 grey bytes; a byte >= thr becomes white (1). Rows
 // of `gstride` bytes in, packed rows of `stride` 32-bit words out; bits past
 // the width are 0. ALIGNED: the grey pointer and pitch are 16-byte aligned.
-template <bool ALIGNED>
+// NT: non-temporal stores (packed images too large to stay cached for the
+// pass that reads them next).
+template <bool ALIGNED, bool NT>
 __global__ void __launch_bounds__(256) k_pack(const uint8_t* grey, int64_t gstride, uint32_t* out,
                                               int64_t stride, int32_t height, int32_t width,
                                               int32_t wd, uint32_t thr) {
@@ -44,7 +46,9 @@ __global__ void __launch_bounds__(256) k_pack(const uint8_t* grey, int64_t gstri
     const int j = (int)(t - y * wd);
     const uint8_t* rp = grey + y * gstride;
     const GreyBlocks<ALIGNED> q = load_grey_word<ALIGNED, false>(rp, j, width);
-    out[y * stride + j] = grey_word<ALIGNED>(q, rp, thr) & valid_bits(j, width);
+    const uint32_t v = grey_word<ALIGNED>(q, rp, thr) & valid_bits(j, width);
+    if constexpr (NT) __builtin_nontemporal_store(v, out + y * stride + j);
+    else out[y * stride + j] = v;
 }
 
 // Workgroups of one grey-band launch at most (2^22 x 512 threads stays
@@ -78,19 +82,32 @@ int launch_grey_band(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int i
 }
 
 // Rows that start on 16-byte boundaries (pointer and pitch) load two
-// blocks per word, others three. Streaming (non-temporal) loads and stores
-// only when asked for: bands re-read their first and last rows from the
-// cache, and cached was faster at every size measured (8192^2 to 65536^2).
+// blocks per word, others three. The cache policy: AUTO (the built-in)
+// keeps the loads cached, since bands re-read their first and last rows
+// from the cache, and makes the stores non-temporal, since the edge map is
+// not read back (8192^2 / 16384^2 / 65536^2: 17.3 / 54.5 / 835 us against
+// 18.5 / 58.3 / 864 us with cached stores); NORMAL keeps both cached;
+// STREAM makes both non-temporal (slower at every size measured: a lane's
+// two loads take alternate 16-byte halves of the same cache lines in two
+// instructions, and non-temporal loads fetch such lines again for the
+// second; a wavefront reading 1 KiB contiguous per load with non-temporal
+// loads, its lanes then exchanging half-words, ran at the AUTO policy's
+// speed, not faster).
+template <int MODE, bool ALIGNED>
+int launch_grey_aligned(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int invert,
+                        hipStream_t stream) {
+    if (c.cache_policy == EDGE_CACHE_STREAM)
+        return launch_grey_band<MODE, ALIGNED, StreamingStrip>(g, c, bw, invert, stream);
+    if (c.cache_policy == EDGE_CACHE_NORMAL)
+        return launch_grey_band<MODE, ALIGNED, CachedStrip>(g, c, bw, invert, stream);
+    return launch_grey_band<MODE, ALIGNED, StreamOutStrip>(g, c, bw, invert, stream);
+}
+
 template <int MODE>
 int launch_grey(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int invert, bool aligned,
                 hipStream_t stream) {
-    const bool nt = c.cache_policy == EDGE_CACHE_STREAM;
-    if (aligned) {
-        return nt ? launch_grey_band<MODE, true, StreamingStrip>(g, c, bw, invert, stream)
-                  : launch_grey_band<MODE, true, CachedStrip>(g, c, bw, invert, stream);
-    }
-    return nt ? launch_grey_band<MODE, false, StreamingStrip>(g, c, bw, invert, stream)
-              : launch_grey_band<MODE, false, CachedStrip>(g, c, bw, invert, stream);
+    return aligned ? launch_grey_aligned<MODE, true>(g, c, bw, invert, stream)
+                   : launch_grey_aligned<MODE, false>(g, c, bw, invert, stream);
 }
 
 int grey_edges_launch(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int invert,
@@ -103,14 +120,21 @@ int grey_edges_launch(const Geom& g, const edge_launch_cfg& c, uint32_t bw, int 
 }
 
 int pack_launch(const uint8_t* grey, int64_t gstride, uint32_t* out, int64_t stride,
-                int32_t height, int32_t width, int32_t wd32, uint32_t thr, bool aligned,
+                int32_t height, int32_t width, int32_t wd, uint32_t thr, bool aligned, bool nt,
                 int64_t blocks, hipStream_t s) {
-    if (aligned)
-        hipLaunchKernelGGL(k_pack<true>, dim3((uint32_t)blocks), dim3(256), 0, s, grey, gstride,
-                           out, stride, height, width, wd32, thr);
+    const dim3 grid((uint32_t)blocks), block(256);
+    if (aligned && nt)
+        hipLaunchKernelGGL((k_pack<true, true>), grid, block, 0, s, grey, gstride, out, stride,
+                           height, width, wd, thr);
+    else if (aligned)
+        hipLaunchKernelGGL((k_pack<true, false>), grid, block, 0, s, grey, gstride, out, stride,
+                           height, width, wd, thr);
+    else if (nt)
+        hipLaunchKernelGGL((k_pack<false, true>), grid, block, 0, s, grey, gstride, out, stride,
+                           height, width, wd, thr);
     else
-        hipLaunchKernelGGL(k_pack<false>, dim3((uint32_t)blocks), dim3(256), 0, s, grey, gstride,
-                           out, stride, height, width, wd32, thr);
+        hipLaunchKernelGGL((k_pack<false, false>), grid, block, 0, s, grey, gstride, out, stride,
+                           height, width, wd, thr);
     return launch_status();
 }
 

@@ -130,9 +130,10 @@ int peel_launch_24_31(const edgek::Geom& g, const edge_launch_cfg& c, uint32_t b
 // kernel mode (kModePlain / kModeFull / kModeClause2) chosen at run time.
 int grey_edges_launch(const edgek::Geom& g, const edge_launch_cfg& c, uint32_t bw, int invert,
                       bool aligned, int kmode, hipStream_t s);
-// Threshold + pack: one thread per 32-bit output word, `blocks` blocks of 256.
+// Threshold + pack: one thread per 32-bit output word, `blocks` blocks of
+// 256; nt: non-temporal stores.
 int pack_launch(const uint8_t* grey, int64_t gstride, uint32_t* out, int64_t stride,
-                int32_t height, int32_t width, int32_t wd32, uint32_t thr, bool aligned,
+                int32_t height, int32_t width, int32_t wd32, uint32_t thr, bool aligned, bool nt,
                 int64_t blocks, hipStream_t s);
 
 }  // namespace edgeh

@@ -603,6 +603,8 @@ edge_launch_cfg default_strips(int64_t height, int64_t wd32) {
 // traffic up (measured: 3.12 against 3.30 us at 4096^2, 4 MiB; equal at
 // 3000^2); smaller images stay cached.
 constexpr int64_t kStreamBytes = 4ll << 20;
+// Threshold + pack: packed output bytes from which its stores stream.
+constexpr int64_t kPackStreamBytes = 16ll << 20;
 
 edge_launch_cfg default_batch() {
     edge_launch_cfg c{};
@@ -1073,10 +1075,14 @@ int edge_threshold_pack(const void* grey, int64_t grey_stride_bytes, int thresho
     const int64_t blocks = ceil_div(threads, 256);
     if (!grid_fits(blocks, 256)) return EDGE_ERR_UNSUPPORTED;
     const bool aligned = (uintptr_t)grey % 16 == 0 && grey_stride_bytes % 16 == 0;
+    // packed output from 16 MiB up stored non-temporally (16384^2 / 32768^2
+    // / 65536^2: 52.3 / 204 / 807 us against 53.4 / 213 / 844 us; equal up
+    // to 8192^2, where a following edge pass still finds the output cached)
+    const bool nt = (int64_t)height * wd32 * 4 >= kPackStreamBytes;
     hipStream_t s = (hipStream_t)hip_stream;
     return pack_launch((const uint8_t*)grey, grey_stride_bytes, (uint32_t*)out, stride_words * per,
-                       (int32_t)height, (int32_t)width, wd32, (uint32_t)threshold, aligned, blocks,
-                       s);
+                       (int32_t)height, (int32_t)width, wd32, (uint32_t)threshold, aligned, nt,
+                       blocks, s);
 }
 
 int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int threshold, void* out,
@@ -1118,13 +1124,13 @@ int edge_threshold_edges(const void* grey, int64_t grey_stride_bytes, int thresh
     if (cfg) {
         c = *cfg;
     } else {
-        // bands of 8 wavefronts x 2 rows (16 rows loaded, 14 out), cached:
-        // measured 16.5 / 54.0 / 849 us at 8192^2 / 16384^2 / 65536^2,
-        // within 1-2% of the best band shape at each and level with the
-        // threshold-and-pack pass alone
+        // bands of 8 wavefronts x 2 rows (16 rows loaded, 14 out), cached
+        // loads and non-temporal stores: within 1-2% of the best band shape
+        // at 8192^2, 16384^2 and 65536^2, and faster than threshold-and-pack
+        // alone at each
         c.vec_words = 1;
         c.blocks_per_cu = 1;
-        c.cache_policy = EDGE_CACHE_NORMAL;
+        c.cache_policy = EDGE_CACHE_AUTO;
         c.rows_per_tile = 2;
         c.waves_per_block = 8;
     }

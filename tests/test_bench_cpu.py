@@ -56,6 +56,15 @@ def test_traffic_takes_the_indexed_table(tmp_path):
     assert bench.measured_traffic(str(p), 2) is None        # no third table
 
 
+def test_traffic_hash_covers_every_kernel_source():
+    import glob
+    import os
+    csrc = os.path.join(bench.ROOT, "paper_1401_5245_amd", "csrc")
+    found = {os.path.relpath(p, bench.ROOT) for p in glob.glob(os.path.join(csrc, "*"))}
+    assert set(bench.KERNEL_SOURCES) == found
+    assert "paper_1401_5245_amd/csrc/edge_grey.hip" in bench.KERNEL_SOURCES
+
+
 def test_host_cores_bounded():
     assert 1 <= bench.host_cores() <= 16
 

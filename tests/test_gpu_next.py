@@ -1,5 +1,7 @@
 """Direction planes (section 4) and threshold packing (section 7) on the
 GPU, bit-exact against the oracle."""
+import itertools
+
 import numpy as np
 import pytest
 import torch
@@ -104,6 +106,29 @@ def test_threshold_pack(word_bits, H, W):
                                           host[:, :-1])
 
 
+@pytest.mark.parametrize("gpad", [0, 5])
+def test_threshold_pack_streaming_stores(gpad):
+    """Packed output of 16 MiB or more is stored non-temporally: 8192 rows
+    of 16448 pixels (16.4 MiB packed) with an aligned and an unaligned grey
+    pitch, the stride word after each row left untouched."""
+    import paper_1401_5245_amd as em
+    H, W = 8192, 16448
+    grey = images.grey_image(H, W, seed=41 + gpad)
+    gs = W + gpad
+    g = np.zeros((H, gs), np.uint8)
+    g[:, :W] = grey
+    gt = torch.from_numpy(g).cuda()
+    S = row_words(W, 64) + 1
+    log(f"threshold pack with streaming stores: {H} x {W}, grey pitch {gs}")
+    out = to_device_words(np.full((H, S), 0x5A5A5A5A5A5A5A5A, dtype=np.uint64))
+    em.threshold_pack(gt, out, H, W, 128, grey_stride=gs, stride_words=S)
+    torch.cuda.synchronize()
+    host = out.cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(pack_rows(oracle.threshold(grey, 128), 64, S)[:, :-1],
+                                  host[:, :-1])
+    assert (host[:, -1] == np.uint64(0x5A5A5A5A5A5A5A5A)).all()
+
+
 @pytest.mark.parametrize("word_bits", [32, 64])
 @pytest.mark.parametrize("H,W", [(1, 1), (2, 31), (5, 33), (9, 1000), (4, 2048), (7, 2049),
                                  (33, 4100), (3, 8200)])
@@ -197,8 +222,9 @@ def test_threshold_edges_band_heights(waves, rows):
     while waves * rw < 4:
         rw *= 2
     ob = waves * rw - 2
-    cfg = dict(vec_words=1, rows_per_tile=rows, waves_per_block=waves, cache_policy=1)
-    for H in sorted({1, 2, 3, ob - 1, ob, ob + 1, 2 * ob - 1, 2 * ob + 1} - {0}):
+    for H, cache in itertools.product(sorted({1, 2, 3, ob - 1, ob, ob + 1, 2 * ob - 1,
+                                              2 * ob + 1} - {0}), (0, 1)):
+        cfg = dict(vec_words=1, rows_per_tile=rows, waves_per_block=waves, cache_policy=cache)
         for W in (2048, 4096 + 37):
             grey = images.grey_image(H, W, seed=H * 3 + W + waves)
             gt = torch.from_numpy(np.ascontiguousarray(grey)).cuda()
@@ -213,10 +239,11 @@ def test_threshold_edges_band_heights(waves, rows):
                 clauses = oracle.CLAUSE2 if c2 else (3 if mode == "full" else oracle.CLAUSE1)
                 want = oracle.edge(binary, border=border, clauses=clauses, invert=inv)
                 assert_same(unpack_rows(out.cpu().numpy().view(np.uint64), W), want,
-                            f"H={H} W={W} {border} {mode} c2={c2}")
+                            f"H={H} W={W} {border} {mode} c2={c2} cache={cache}")
 
 
-@pytest.mark.parametrize("rows,waves,cache", [(1, 1, 1), (3, 2, 2), (16, 8, 1), (64, 4, 2)])
+@pytest.mark.parametrize("rows,waves,cache", [(1, 1, 1), (3, 2, 2), (16, 8, 1), (64, 4, 2),
+                                              (2, 8, 0), (4, 4, 0)])
 def test_threshold_edges_cfgs(rows, waves, cache):
     import paper_1401_5245_amd as em
     H, W = 130, 5000
