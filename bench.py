@@ -598,6 +598,7 @@ def next_rows_65536(torch, em, tm, steps=20):
         for p in range(4):
             got = unpack_rows(out4[p, r:r + 1].cpu().numpy().view(np.uint64), W)[0]
             ok &= bool(np.array_equal(got, fe[p][r - lo]))
+    warm_by_time(torch, lambda: em.edge_directions(inp, out4, H, W))
     ms = tm.per_call_ms(lambda i: em.edge_directions(inp, out4, H, W), steps)
     nbytes = 5 * H * (W // 8)
     res["directions"] = {"workload": "65536x65536 tiled glyph page (seed 22), uint64: four "
@@ -619,6 +620,7 @@ def next_rows_65536(torch, em, tm, steps=20):
         lo, win = window(binary_tile, r)
         got = unpack_rows(out[r:r + 1].cpu().numpy().view(np.uint64), W)[0]
         ok &= bool(np.array_equal(got, oracle.edge(win)[r - lo]))
+    warm_by_time(torch, lambda: em.threshold_edges(gt, out, H, W, 128))
     ms = tm.per_call_ms(lambda i: em.threshold_edges(gt, out, H, W, 128), steps)
     nbytes = H * W + H * (W // 8)
     res["threshold_edges"] = {"workload": "65536x65536 tiled grey image (seed 7), threshold 128, "
