@@ -124,7 +124,9 @@ typedef struct edge_image_desc {
  *                   1..32; ignored by the single-image calls.
  *   cache_policy    EDGE_CACHE_AUTO (by image size), EDGE_CACHE_NORMAL or
  *                   EDGE_CACHE_STREAM (non-temporal loads and stores);
- *                   single images only, batches use EDGE_CACHE_NORMAL.
+ *                   single images only, batches use EDGE_CACHE_NORMAL;
+ *                   edge_threshold_edges reads AUTO as cached loads with
+ *                   non-temporal stores.
  *   shape           how a single image's rows of more than 32 words are
  *                   cut into work: EDGE_SHAPE_STRIP (a wavefront walks its
  *                   rows with a few rows in flight), EDGE_SHAPE_TILE (a
